@@ -1,0 +1,50 @@
+"""The pins catch plausible mistakes: each test builds the oracle with one
+deliberate error (on the CPU) and shows that a pin from test_oracle.py
+rejects it.  The correct oracle passes the same checks."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import golden_io
+
+
+def _golden_ok(orc):
+    for c in golden_io.stage_cases():
+        st = orc.stages(c["keys"], c["p"], c["s"], c["mode"], c["seed"])
+        if list(zip(st["sample_ord"].tolist(), st["sample_tag"].tolist())) != c["sample"]:
+            return False
+        if list(zip(st["spl_ord"].tolist(), st["spl_tag"].tolist())) != c["splitters"]:
+            return False
+        if st["counts"].tolist() != c["counts"]:
+            return False
+    return True
+
+
+def _stable_ok(orc):
+    g = np.random.default_rng(1)
+    for n in [5, 50, 500]:
+        keys = g.integers(-3, 3, n).astype(np.int32)
+        if not np.array_equal(orc.stable_perm(keys), np.argsort(keys, kind="stable")):
+            return False
+    return True
+
+
+CASES = {
+    1: ("merge takes the right run on equal keys", _stable_ok),
+    2: ("splitter rank off by one", _golden_ok),
+    3: ("a splitter opens its bucket instead of closing it", _golden_ok),
+    4: ("padded segment length rounded down", _golden_ok),
+    5: ("tags ignored when keys are equal", _golden_ok),
+    6: ("signed keys compared without the sign flip", _stable_ok),
+}
+
+
+def test_correct_oracle_passes():
+    assert _golden_ok(oracle._get()) and _stable_ok(oracle._get())
+
+
+@pytest.mark.parametrize("plant", sorted(CASES))
+def test_planted_mistake_is_caught(plant, tmp_path):
+    what, check = CASES[plant]
+    bad = oracle.planted(plant, str(tmp_path))
+    assert not check(bad), f"planted mistake not caught: {what}"
