@@ -1,0 +1,163 @@
+#!/usr/bin/env python
+"""Benchmark of the MI355X sample sort.
+
+Default workload: 2^26 int32 keys (uniform, seeded, synthetic), keys only,
+random oversampling with p = 4096 buckets and oversampling s = 16, resident
+in HBM before the timed region.  One step = one full sort (sample, sample
+sort, splitters, classify, scan, stable scatter, bucket sorts).
+
+Prints ONE JSON line with Gkeys/s, the roofline of the dominant kernel
+(algorithmic bytes / its HIP-event time, against 8 TB/s HBM) and the CPU
+oracle's rate on a bounded sample of the same workload.
+
+Other workloads (--workload): pairs (2^27 uint64 keys + uint32 payload),
+segmented (20,000 log-uniform segments, one graph-captured call vs one call
+per segment), autograd (64 x 2^18 float32 rows, SortFn forward/backward vs
+per-row calls).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="sort", choices=["sort", "pairs", "segmented", "autograd"])
+    ap.add_argument("--log2n", type=int, default=26)
+    ap.add_argument("--p", type=int, default=4096)
+    ap.add_argument("--s", type=int, default=16)
+    ap.add_argument("--sampling", default="random", choices=["random", "regular"])
+    ap.add_argument("--dist", default="uniform")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-log2n", type=int, default=24, help="CPU baseline sample size (log2)")
+    ap.add_argument("--profile", action="store_true", help="per-kernel table on stderr")
+    return ap.parse_args()
+
+
+def cpu_baseline(keys, log2n, runs=2):
+    """The oracle (single-threaded C stable merge sort) on a prefix of the
+    same input; Gkeys/s."""
+    import oracle
+    sample = keys[: min(keys.size, 1 << log2n)].copy()
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.stable_perm(sample)
+        ts.append(time.perf_counter() - t0)
+    t = sum(ts) / len(ts)
+    return {"value": round(sample.size / t / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"first 2^{int(log2n)} keys of the same input, mean of {runs} runs ({t:.2f} s each)"}
+
+
+def fingerprint(a):
+    import numpy as np
+    v = a.view(np.uint32 if a.dtype.itemsize == 4 else np.uint64).astype(np.uint64)
+    return (int(v.sum()), int((v * v).sum()), int(np.bitwise_xor.reduce(v)))
+
+
+def kernel_table(rep, steps):
+    return {k: {"ms_per_step": round(ms / steps, 5), "launches_per_step": round(c / steps, 3)}
+            for k, (ms, c) in rep.items() if c}
+
+
+def roofline_of(rep, steps, bytes_per_step):
+    """Dominant kernel: the kind with the largest time; achieved = its
+    algorithmic bytes per step / its time per step."""
+    tot = {k: ms for k, (ms, c) in rep.items() if c}
+    dom = max(tot, key=tot.get)
+    t = tot[dom] / steps / 1e3
+    b = bytes_per_step.get(dom)
+    if not b:
+        return dom, None
+    ach = b / t / 1e9
+    return dom, {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                 "bytes_per_launch": b, "ms_per_launch": round(t * 1e3, 5)}
+
+
+def bench_sort(args):
+    import numpy as np
+    import torch
+
+    from paper_1608_08648_amd import api, native, workloads
+
+    n = 1 << args.log2n
+    dev = torch.device("cuda:0")
+    seed = workloads.seed_for(1, workloads.DISTRIBUTIONS.index(args.dist))
+    keys = workloads.keys_2p26(n, args.dist, seed, np.int32)
+    kd = torch.from_numpy(keys).to(dev)
+    out = torch.empty_like(kd)
+    prm = api.params(p=args.p, s=args.s, sampling=args.sampling, seed=1234, tile=args.tile)
+    info = api.stage_layout(n, native.SS_I32, native.SS_V_NONE, prm)
+    ws = api._workspace(api.workspace_size(n, native.SS_I32, native.SS_V_NONE, prm), dev)
+    for _ in range(args.warmup):
+        api.sort_keys(kd, prm, out=out, ws=ws)
+    torch.cuda.synchronize()
+    native.profile_enable(True, max_launches=64 * (args.steps + 1))
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(args.steps):
+        api.sort_keys(kd, prm, out=out, ws=ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    native.profile_collect()
+    rep = native.profile_report()
+    native.profile_enable(False)
+    status = api.status(ws)
+    got = out.cpu().numpy()
+    ok = bool(np.all(got[1:] >= got[:-1])) and fingerprint(got) == fingerprint(keys)
+    kb = 4
+    bytes_per_step = {"classify": kb * n, "scatter": 2 * kb * n, "bucket_sort": 2 * kb * n}
+    dom, roof = roofline_of(rep, args.steps, bytes_per_step)
+    gk = n / (ms / 1e3) / 1e9
+    res = {
+        "metric": "Gkeys/s and % of HBM roofline, sample sort 2^26 int32; batched vs per-segment",
+        "value": round(gk, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i32", "data": "synthetic",
+        "config": {"workload": f"sample sort of 2^{args.log2n} int32 keys ({args.dist}), keys only",
+                   "n": n, "p": args.p, "p_eff": info.p_eff, "s": args.s, "sampling": args.sampling,
+                   "levels_below_top": info.levels, "dist": args.dist, "seed": seed},
+        "hbm_frac_20B_per_key": round(gk * 20 / HBM_PEAK_GBS, 4),
+        "roofline": roof,
+        "kernels": kernel_table(rep, args.steps),
+        "check": "sorted+multiset" if ok else "FAILED",
+        "device_status": status,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(keys, args.cpu_log2n)
+    return res, ok
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the sort of one GPU's share is what it "
+                                   "measures; --gpus must be 1"}))
+        sys.exit(2)
+    if args.workload == "sort":
+        res, ok = bench_sort(args)
+    else:
+        from paper_1608_08648_amd import benchmarks
+        res, ok = getattr(benchmarks, "bench_" + args.workload)(args)
+    print(json.dumps(res), flush=True)
+    if not ok:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * samplesort.h -- C ABI of the MI355X (gfx950) oversampling sample sort.
+ *
+ * The method (Gerbessiotis, arXiv 1608.08648): draw a sample of the keys
+ * (random oversampling, Alg. 2 step 2, or deterministic regular
+ * oversampling, Alg. 1 steps 1-2), sort it, take p-1 equidistant splitters
+ * (step 3), split every key into one of p buckets (step 4; ties between
+ * equal keys broken by input position, Section 2.2), and sort every bucket
+ * on its own so the buckets concatenate into the output (Section 1).  Here
+ * sampling precedes the split (the traditional organisation described in
+ * Section 1 and after Claim 1) and every step runs in HIP kernels on one
+ * GPU.
+ *
+ * Conventions shared by every entry point:
+ *  - All array arguments are DEVICE pointers unless stated otherwise.  The
+ *    caller owns every buffer, including the workspace `ws`; no entry point
+ *    allocates device memory, so calls may be captured into a HIP graph.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is enqueued on it; the calls return before the GPU finishes.
+ *  - The return value covers argument checks and launch errors only:
+ *    SS_OK (0) or a negative SS_E* code, with a message in ss_last_error().
+ *    Conditions detected on the device are reported by ss_status().
+ *  - In-place use is allowed (keys_in == keys_out, vals_in == vals_out);
+ *    partial overlap of an input with an output is rejected (SS_EINVAL).
+ *  - The result is always the stable order: equal keys keep their input
+ *    order (Section 1's definition).  `stable = 0` is accepted and gives the
+ *    same result.
+ *  - Keys order as integers (unsigned or two's complement) or, for floats,
+ *    by IEEE 754 totalOrder (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN).
+ */
+#ifndef SAMPLESORT_H
+#define SAMPLESORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* key types */
+enum { SS_U32 = 0, SS_I32 = 1, SS_F32 = 2, SS_U64 = 3, SS_I64 = 4, SS_F64 = 5 };
+
+/* payload types: a payload is moved bit-exactly with its key.
+ * SS_V_IOTA32 / SS_V_IOTA64: no payload is read (vals_in must be NULL); the
+ * payload of each key is its index within its array or segment, written as
+ * uint32 / int64, i.e. the stable sorting permutation. */
+enum { SS_V_NONE = 0, SS_V_B32 = 1, SS_V_B64 = 2, SS_V_IOTA32 = 3, SS_V_IOTA64 = 4 };
+
+/* sampling rule */
+enum { SS_RANDOM = 0,   /* Alg. 2: p*s-1 keys drawn uniformly (with replacement) */
+       SS_REGULAR = 1   /* Alg. 1: p blocks, s*p evenly spaced keys per sorted block */ };
+
+/* flags */
+#define SS_F_EXPORT_STAGES  1u  /* keep the top-level sample, splitters and bucket counts in ws */
+#define SS_F_FORCE_PIPELINE 2u  /* run the sampling pipeline even when n fits one work-group */
+#define SS_F_NO_RECURSION   4u  /* plan no split level below the top one: a bucket too large for
+                                   one work-group is then sorted by a one-work-group merge sort
+                                   (slow; for tests of that path) */
+
+/* return codes */
+enum { SS_OK = 0, SS_EINVAL = -1, SS_EWORKSPACE = -2, SS_EHIP = -3, SS_EDEVICE = -4 };
+
+/* Largest bucket count: the splitter search tree of one level lives in LDS. */
+#define SS_P_MAX 4096u
+
+/*
+ * Parameters of the method.
+ *  p        requested bucket count, a power of two in [2, SS_P_MAX].  The
+ *           effective count is the largest power of two <= p that keeps the
+ *           paper's preconditions: p <= n (Theorem 1), p*s < n/2 for random
+ *           sampling (Claim 1), 4*s*p^2 <= n for regular sampling (the
+ *           sample s*p^2 must be small against n, Theorem 1).
+ *  s        oversampling factor as the paper states it per rule: RANDOM
+ *           samples p*s-1 keys and takes every s-th as a splitter (Alg. 2);
+ *           REGULAR takes s*p keys from each of the p sorted blocks (the
+ *           paper's r = s, per-block sample r*p, Alg. 1) and every (s*p)-th
+ *           of the s*p^2 samples as a splitter.  s >= 1.
+ *  sampling SS_RANDOM or SS_REGULAR (applies to the top level; buckets too
+ *           large for one work-group are split again with random sampling).
+ *  stable   accepted for interface compatibility; the result is always stable.
+ *  seed     seed of the counter-based generator (SplitMix64) behind random
+ *           sampling; the same seed gives the same sample.
+ *  flags    SS_F_* bits.
+ *  tile     keys per work-group in the split passes (0 = chosen per p).
+ */
+typedef struct ss_params {
+    uint32_t p;
+    uint32_t s;
+    int32_t sampling;
+    int32_t stable;
+    uint64_t seed;
+    uint32_t flags;
+    uint32_t tile;
+} ss_params;
+
+/* Where the top-level stages sit inside the workspace after a call with
+ * SS_F_EXPORT_STAGES (byte offsets from ws; counts in elements).
+ *  sample_ord / sample_tag : uint64[m]  sorted sample; ord = the key's
+ *                            order-preserving unsigned image, tag = input index
+ *  spl_ord / spl_tag       : uint64[p_eff-1] splitters (same encoding)
+ *  counts                  : uint64[p_eff]  keys per bucket
+ * p_eff == 1 means the call sorts directly with no sampling (n fits one
+ * work-group, or no p >= 2 meets the preconditions). */
+typedef struct ss_stage_info {
+    uint32_t p_eff;
+    uint32_t stride;      /* splitter i is the (i*stride)-th smallest sample */
+    uint64_t m;           /* sample size */
+    uint64_t sample_ord, sample_tag, spl_ord, spl_tag, counts;
+    uint32_t direct;      /* 1 if no sampling pass runs */
+    uint32_t levels;      /* split levels planned below the top one */
+} ss_stage_info;
+
+/* Last error message of the calling thread ("" if none).  Host only. */
+const char *ss_last_error(void);
+
+/* Workspace bytes a sample_sort_keys / sample_sort_pairs call with these
+ * arguments needs.  Host only, no device call.  val_type = SS_V_NONE for a
+ * keys-only sort. */
+int ss_workspace_size(size_t n, int key_type, int val_type, const ss_params *prm, size_t *bytes_out);
+
+/* Layout of the exported stages for the same arguments.  Host only. */
+int ss_stage_layout(size_t n, int key_type, int val_type, const ss_params *prm, ss_stage_info *info);
+
+/* Sort n keys ascending (stable).  keys_in/keys_out: device arrays of n keys
+ * of key_type.  ws: device workspace of at least ss_workspace_size bytes,
+ * 256-byte aligned; its contents on entry do not matter. */
+int sample_sort_keys(const void *keys_in, void *keys_out, size_t n, int key_type,
+                     const ss_params *prm, void *ws, size_t ws_bytes, void *stream);
+
+/* Sort n (key, payload) pairs by key, stable; the payload follows its key.
+ * vals_in: device array of n payloads of val_type (NULL for the IOTA types);
+ * vals_out: device array of n payloads (uint32 for SS_V_B32/SS_V_IOTA32,
+ * 8-byte for SS_V_B64/SS_V_IOTA64). */
+int sample_sort_pairs(const void *keys_in, const void *vals_in, void *keys_out, void *vals_out,
+                      size_t n, int key_type, int val_type, const ss_params *prm,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for segmented_sort: `total` keys in `num_segments`
+ * segments, none longer than `max_seg_len` (0 = unknown, taken as total). */
+int ss_segmented_workspace_size(size_t total, size_t num_segments, size_t max_seg_len, int key_type,
+                                int val_type, const ss_params *prm, size_t *bytes_out);
+
+/* Sort every segment [offsets[g], offsets[g+1]) independently (stable), for
+ * g < num_segments, in one fixed sequence of kernel launches whatever the
+ * segment sizes (so the call can be captured into a HIP graph and replayed).
+ * d_offsets: DEVICE int64[num_segments+1], non-decreasing, offsets[0] may be
+ * > 0; `total` must equal offsets[num_segments] and `max_seg_len` bound
+ * every segment length (both host values).  Empty segments are allowed.  For
+ * the IOTA payload types the payload is the index within the segment.
+ * prm may be NULL: then every size class uses tuned defaults; otherwise
+ * prm->s, prm->seed and prm->tile apply to every split, and prm->p caps the
+ * buckets per segment. */
+int segmented_sort(const void *keys_in, const void *vals_in, void *keys_out, void *vals_out,
+                   const int64_t *d_offsets, size_t num_segments, size_t total, size_t max_seg_len,
+                   int key_type, int val_type, const ss_params *prm, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* Backward of a row-wise sort y[r, j] = x[r, perm[r, j]]: the gradient goes
+ * back through the permutation, grad_x[r, perm[r, j]] = grad_y[r, j].  Each
+ * row of perm must be a permutation of 0..row_len-1 (then every grad_x
+ * element is written exactly once).  elem_bytes = 2, 4 or 8.  grad_y,
+ * grad_x: device [rows, row_len]; perm: device int64 [rows, row_len]. */
+int ss_scatter_grad(const void *grad_y, const int64_t *perm, void *grad_x, size_t rows, size_t row_len,
+                    int elem_bytes, void *stream);
+
+/* Wait for `stream`, then read the device status word of the last call that
+ * used `ws`: SS_OK, or SS_EDEVICE if the device reported a condition (the
+ * message names it). */
+int ss_status(const void *ws, void *stream);
+
+/* Per-kernel timing, for benchmarks.  While enabled (on != 0), every kernel
+ * the library launches is bracketed by two HIP events recorded on the
+ * caller's stream (from a pool of `max_launches` event pairs created here;
+ * this call may allocate host/driver resources and must not be made during
+ * graph capture).  ss_profile_collect() waits for the recorded events and
+ * adds their durations to per-kernel totals; ss_profile_report(i, ...)
+ * returns the name, total milliseconds and launch count of kernel kind i
+ * (SS_EINVAL past the last kind).  ss_profile_enable(0) frees the pool and
+ * clears the totals. */
+int ss_profile_enable(int on, int max_launches);
+int ss_profile_collect(void);
+int ss_profile_report(int kind, const char **name, double *total_ms, uint64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAMPLESORT_H */

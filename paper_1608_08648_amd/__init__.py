@@ -1,17 +1,19 @@
 """MI355X-native oversampling sample sort (arXiv 1608.08648).
 
 The sort runs in hand-written HIP kernels for gfx950 behind the C ABI
-declared in ``include/samplesort.h``; this package only marshals torch
-tensors to it.  The public functions are re-exported from :mod:`.api`.
+declared in ``include/samplesort.h``; :mod:`.api` only marshals torch
+tensors to it (``sort_keys``, ``sort_pairs``, ``segmented_sort``,
+``scatter_grad``, ``SortFn``/``sort``).
 """
-from . import workloads  # noqa: F401
+import importlib
 
-__all__ = ["workloads"]
+_SUBMODULES = ("api", "native", "workloads", "build")
 
 
 def __getattr__(name):
-    # the torch-facing API loads the native library on first use
-    from . import api
+    if name in _SUBMODULES:
+        return importlib.import_module(f"{__name__}.{name}")
+    api = importlib.import_module(f"{__name__}.api")
     if hasattr(api, name):
         return getattr(api, name)
     raise AttributeError(name)

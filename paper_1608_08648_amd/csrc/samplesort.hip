@@ -1,0 +1,803 @@
+// Host side of the sample sort: argument checks, the plan (effective p,
+// sample size, split levels, workspace layout) and the launch sequence.
+// Every entry point only enqueues kernels on the caller's stream; nothing
+// here allocates device memory or waits for the GPU (except ss_status).
+#include "../../include/samplesort.h"
+#include "ss_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+using namespace ss;
+
+namespace {
+
+thread_local char g_err[512];
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(x)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess) return fail(SS_EHIP, "%s: %s", #x, hipGetErrorString(e_));    \
+  } while (0)
+#define LAUNCH_CHECK()                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = hipGetLastError();                                                  \
+    if (e_ != hipSuccess) return fail(SS_EHIP, "launch: %s", hipGetErrorString(e_));    \
+  } while (0)
+
+// ---------------------------------------------------------------- profiling
+enum ProfKind {
+  PK_INIT, PK_PLAN, PK_SAMPLE, PK_SAMPLE_SORT, PK_SAMPLE_MERGE, PK_TREE, PK_CLASSIFY, PK_SCAN, PK_SCATTER,
+  PK_BUCKET_SORT, PK_SMALL_SORT, PK_BLOCK_SORT_REGULAR, PK_GRAD, PK_COUNT
+};
+const char* const PROF_NAMES[PK_COUNT] = {
+    "init", "plan", "sample", "sample_sort", "sample_merge", "tree", "classify", "scan", "scatter",
+    "bucket_sort", "small_sort", "regular_blocks", "scatter_grad"};
+
+struct Prof {
+  bool on = false;
+  int cap = 0, used = 0;
+  std::vector<hipEvent_t> ev;       // 2 per launch
+  std::vector<int> kind;
+  double total[PK_COUNT] = {};
+  uint64_t count[PK_COUNT] = {};
+};
+Prof g_prof;
+
+// bracket one launch with events (no-op unless profiling is on)
+struct ProfScope {
+  int slot = -1;
+  hipStream_t st;
+  ProfScope(int k, hipStream_t s) : st(s) {
+    if (!g_prof.on || g_prof.used >= g_prof.cap) return;
+    slot = g_prof.used++;
+    g_prof.kind[slot] = k;
+    hipEventRecord(g_prof.ev[2 * slot], st);
+  }
+  ~ProfScope() {
+    if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot + 1], st);
+  }
+};
+#define LAUNCH(kind, ...)                 \
+  do {                                    \
+    ProfScope prof_scope_((kind), st);    \
+    hipLaunchKernelGGL(__VA_ARGS__);      \
+  } while (0)
+
+struct Types {
+  int kt = 0, vt = 0;
+  int KW = 4, VW = 0;
+  int kind = 0;     // 0 unsigned, 1 signed, 2 float
+  bool iota = false;
+};
+
+int parse_types(int kt, int vt, Types* ty) {
+  if (kt < SS_U32 || kt > SS_F64) return fail(SS_EINVAL, "unknown key_type %d", kt);
+  ty->kt = kt;
+  ty->vt = vt;
+  ty->KW = kt <= SS_F32 ? 4 : 8;
+  ty->kind = (kt == SS_U32 || kt == SS_U64) ? 0 : ((kt == SS_I32 || kt == SS_I64) ? 1 : 2);
+  switch (vt) {
+    case SS_V_NONE: ty->VW = 0; ty->iota = false; break;
+    case SS_V_B32: ty->VW = 4; ty->iota = false; break;
+    case SS_V_B64: ty->VW = 8; ty->iota = false; break;
+    case SS_V_IOTA32: ty->VW = 4; ty->iota = true; break;
+    case SS_V_IOTA64: ty->VW = 8; ty->iota = true; break;
+    default: return fail(SS_EINVAL, "unknown val_type %d", vt);
+  }
+  return SS_OK;
+}
+
+uint32_t small_cap(int KW, int VW) {
+  int s = KW + VW;
+  return (uint32_t)NT * (s <= 4 ? 64 : (s <= 8 ? 32 : 16));
+}
+uint32_t sample_cap(int KW) { return (uint32_t)NT * (KW == 4 ? 32 : 16); }
+uint32_t split_chunk(int KW, int VW) { return (uint32_t)NT * ((KW + VW <= 4) ? 8 : 4); }
+
+constexpr size_t ALIGN = 256;
+struct Layout {
+  size_t cur = 0;
+  size_t take(size_t bytes) {
+    size_t o = (cur + ALIGN - 1) & ~(ALIGN - 1);
+    cur = o + bytes;
+    return o;
+  }
+};
+
+uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Largest bucket of a random split relative to the mean, as a planning
+// estimate (the levels below are sized from it; a larger bucket is still
+// sorted correctly, by the next level or the one-work-group fallback).
+double spread(uint32_t s) { return 1.0 + 4.0 / std::sqrt((double)std::max(1u, s)); }
+
+// Effective bucket count: the largest power of two <= p with p <= n
+// (Theorem 1) and p*s < n/2 (Claim 1, random) or 4*s*p^2 <= n (regular).
+uint32_t p_effective(uint64_t n, uint32_t p, uint32_t s, int mode) {
+  uint64_t q = 1;
+  while (q * 2 <= p) q *= 2;
+  for (; q >= 2; q /= 2) {
+    if (q > n) continue;
+    if (mode == SS_RANDOM) {
+      if (2 * q * (uint64_t)s < n) return (uint32_t)q;
+    } else {
+      if (4 * (uint64_t)s * q * q <= n) return (uint32_t)q;
+    }
+  }
+  return 1;
+}
+
+uint32_t default_tile(uint32_t p, uint32_t chunk) {
+  uint64_t t = std::max<uint64_t>(16384, 16ull * p);
+  return (uint32_t)(cdiv(t, chunk) * chunk);
+}
+
+struct LevelPlan {
+  uint32_t tile = 0, seg_cap = 0, pmax = 256, p_cap = 256, target = 0, s = 1;
+  uint64_t samp_cap = 0, tiles_cap = 0, hist_cap = 0, bkt_cap = 0;
+  size_t o_segs = 0, o_sord = 0, o_stag = 0, o_tree = 0, o_ttag = 0, o_hist = 0, o_part = 0;
+};
+
+struct LevelsPlan {
+  int nlev = 0;
+  LevelPlan lv[MAX_LEVELS];
+  bool big_sample = false;  // top level sample larger than one work-group (single segment only)
+  int merge_passes = 0;
+  size_t o_sord2 = 0, o_stag2 = 0;
+};
+
+// Shapes of the split levels.  Level 0 either has one segment with given p0
+// and sample size m0 (single sort) or up to seg_cap0 segments sized on the
+// device (p0 == 0).  N = total elements, maxlen0 = longest top segment.
+void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint64_t maxlen0, uint32_t p0,
+                 uint64_t m0, uint64_t est_max0, uint32_t s, uint32_t p_cap, uint32_t tile_req, bool recurse,
+                 LevelsPlan* P) {
+  const uint32_t C = small_cap(ty.KW, ty.VW);
+  const uint32_t Cs = sample_cap(ty.KW);
+  const uint32_t CH = split_chunk(ty.KW, ty.VW);
+  const double f = spread(s);
+  const uint32_t target = (uint32_t)std::max(1024.0, (double)C / (1.2 * f));
+  P->nlev = 0;
+  uint64_t est = 0;
+  for (int l = 0; l < MAX_LEVELS; l++) {
+    LevelPlan& lv = P->lv[l];
+    lv.s = s;
+    lv.target = target;
+    if (l == 0 && p0) {
+      lv.p_cap = p0;
+      lv.pmax = p0 > 256 ? 4096 : 256;
+      lv.tile = tile_req ? (uint32_t)(cdiv(tile_req, CH) * CH) : default_tile(p0, CH);
+      lv.seg_cap = 1;
+      lv.samp_cap = m0;
+      lv.tiles_cap = cdiv(N, lv.tile);
+      lv.hist_cap = (uint64_t)p0 * lv.tiles_cap;
+      lv.bkt_cap = p0;
+      est = est_max0;
+    } else {
+      lv.p_cap = p_cap;
+      lv.pmax = p_cap > 256 ? 4096 : 256;
+      lv.tile = tile_req ? (uint32_t)(cdiv(tile_req, CH) * CH) : default_tile(p_cap, CH);
+      uint64_t sc = (l == 0) ? seg_cap0 : std::min<uint64_t>(P->lv[l - 1].bkt_cap, N / (C + 1) + 1);
+      sc = std::min<uint64_t>(sc, N / (C + 1) + 1);
+      lv.seg_cap = (uint32_t)std::max<uint64_t>(sc, 1);
+      lv.tiles_cap = N / lv.tile + lv.seg_cap + 1;
+      lv.bkt_cap = std::min<uint64_t>((uint64_t)lv.seg_cap * p_cap, 2 * N / target + 2ull * lv.seg_cap + 2);
+      lv.hist_cap = (uint64_t)p_cap * lv.tiles_cap;
+      lv.samp_cap = std::min<uint64_t>((uint64_t)Cs * lv.seg_cap, (uint64_t)s * lv.bkt_cap);
+      uint64_t len = (l == 0) ? maxlen0 : est;
+      est = (uint64_t)(std::max<double>(target, (double)len / p_cap) * f);
+    }
+    lv.o_segs = L.take(sizeof(SegDesc) * lv.seg_cap);
+    lv.o_sord = L.take((size_t)ty.KW * std::max<uint64_t>(lv.samp_cap, 1));
+    lv.o_stag = L.take(4 * std::max<uint64_t>(lv.samp_cap, 1));
+    lv.o_tree = L.take(8 * std::max<uint64_t>(lv.bkt_cap, 1));
+    lv.o_ttag = (ty.KW == 8) ? L.take(4 * std::max<uint64_t>(lv.bkt_cap, 1)) : 0;
+    lv.o_hist = L.take(4 * std::max<uint64_t>(lv.hist_cap, 1));
+    lv.o_part = L.take(4 * (cdiv(std::max<uint64_t>(lv.hist_cap, 1), SCAN_BLOCK) + 1));
+    if (l == 0 && p0 && m0 > Cs) {
+      P->big_sample = true;
+      P->merge_passes = 0;
+      while (((uint64_t)Cs << P->merge_passes) < m0) P->merge_passes++;
+      P->o_sord2 = L.take((size_t)ty.KW * m0);
+      P->o_stag2 = L.take(4 * m0);
+    }
+    P->nlev = l + 1;
+    if (!recurse || est <= C) break;
+  }
+}
+
+// Full plan of one call.
+struct Plan {
+  Types ty;
+  uint64_t n = 0;          // elements (single) / index range end (segmented)
+  ss_params prm{};
+  bool segmented = false;
+  uint64_t nseg = 0, maxlen = 0;
+  bool direct = false;     // n fits one work-group
+  bool whole = false;      // no valid p: one work-group sorts everything
+  uint32_t p_eff = 1, s = 1, stride = 1;
+  uint64_t m = 0;
+  bool regular = false;
+  LevelsPlan lp;
+  size_t o_ctl = 0, o_tmp = 0, o_vtmp = 0;
+  size_t o_exp_so = 0, o_exp_st = 0, o_exp_po = 0, o_exp_pt = 0, o_exp_cnt = 0;
+  bool exp = false;
+  size_t o_small = 0;      // segmented: small-segment list
+  // regular sampling: sorted blocks and the nested segmented plan
+  size_t o_regk = 0, o_regi = 0, o_regoff = 0, o_nested = 0;
+  Plan* nested = nullptr;
+  size_t bytes = 0;
+  ~Plan() { delete nested; }
+};
+
+int check_params(const ss_params* prm, ss_params* out) {
+  ss_params d{};
+  d.p = 1024;
+  d.s = 8;
+  d.sampling = SS_RANDOM;
+  d.stable = 1;
+  d.seed = 0x5EEDull;
+  if (prm) d = *prm;
+  if (d.p < 2 || d.p > SS_P_MAX || (d.p & (d.p - 1))) return fail(SS_EINVAL, "p = %u: need a power of two in [2, %u]", d.p, SS_P_MAX);
+  if (d.s < 1 || d.s > 4096) return fail(SS_EINVAL, "s = %u: need 1 <= s <= 4096", d.s);
+  if (d.sampling != SS_RANDOM && d.sampling != SS_REGULAR) return fail(SS_EINVAL, "unknown sampling rule %d", d.sampling);
+  *out = d;
+  return SS_OK;
+}
+
+int plan_segmented(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, const Types& ty, const ss_params& prm,
+                   bool user_params);
+
+int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
+  P->ty = ty;
+  P->n = n;
+  P->prm = prm;
+  if (n >= (1ull << 32)) return fail(SS_EINVAL, "n = %llu: at most 2^32-1 keys per array", (unsigned long long)n);
+  const uint32_t C = small_cap(ty.KW, ty.VW);
+  Layout L;
+  P->o_ctl = L.take(sizeof(Ctl));
+  P->regular = prm.sampling == SS_REGULAR;
+  P->p_eff = p_effective(n, prm.p, prm.s, prm.sampling);
+  P->direct = (n <= C && !(prm.flags & SS_F_FORCE_PIPELINE)) || n < 2;
+  if (!P->direct && P->p_eff < 2) P->whole = true;
+  if (P->direct || P->whole) {
+    P->p_eff = 1;
+    P->regular = false;
+    if (P->whole) {
+      P->o_tmp = L.take((size_t)ty.KW * n);
+      P->o_vtmp = ty.VW ? L.take((size_t)ty.VW * n) : 0;
+    }
+    P->bytes = L.cur;
+    return SS_OK;
+  }
+  const uint32_t p = P->p_eff;
+  P->s = prm.s;
+  uint64_t est;
+  if (P->regular) {
+    P->m = (uint64_t)prm.s * p * p;
+    P->stride = prm.s * p;
+    // Lemma 1: no bucket exceeds (S + p) * x, S = s*p, x = ceil(ceil(n/p)/S)
+    uint64_t S = (uint64_t)prm.s * p, x = cdiv(cdiv(n, p), S);
+    est = (S + p) * x;
+  } else {
+    P->m = (uint64_t)p * prm.s - 1;
+    P->stride = prm.s;
+    est = (uint64_t)((double)n / p * spread(prm.s));
+  }
+  P->exp = (prm.flags & SS_F_EXPORT_STAGES) != 0;
+  if (P->exp) {
+    P->o_exp_so = L.take(8 * P->m);
+    P->o_exp_st = L.take(8 * P->m);
+    P->o_exp_po = L.take(8 * (p - 1));
+    P->o_exp_pt = L.take(8 * (p - 1));
+    P->o_exp_cnt = L.take(8 * p);
+  }
+  P->o_tmp = L.take((size_t)ty.KW * n);
+  P->o_vtmp = ty.VW ? L.take((size_t)ty.VW * n) : 0;
+  const bool recurse = !(prm.flags & SS_F_NO_RECURSION);
+  plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp);
+  if (P->regular) {
+    // blocks sorted with their in-block index as payload (Alg. 1 step 1)
+    P->o_regk = L.take((size_t)ty.KW * n);
+    P->o_regi = L.take(4 * n);
+    P->o_regoff = L.take(8 * (p + 1));
+    Types bt = ty;
+    bt.vt = SS_V_IOTA32;
+    bt.VW = 4;
+    bt.iota = true;
+    P->nested = new Plan();
+    ss_params bp = prm;
+    bp.sampling = SS_RANDOM;
+    bp.flags &= SS_F_NO_RECURSION;
+    int rc = plan_segmented(P->nested, n, p, cdiv(n, p), bt, bp, false);
+    if (rc) return rc;
+    P->o_nested = L.take(P->nested->bytes);
+  }
+  P->bytes = L.cur;
+  return SS_OK;
+}
+
+int plan_segmented(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, const Types& ty, const ss_params& prm,
+                   bool user_params) {
+  P->ty = ty;
+  P->n = total;
+  P->prm = prm;
+  P->segmented = true;
+  P->nseg = nseg;
+  if (maxlen == 0 || maxlen > total) maxlen = total;
+  P->maxlen = maxlen;
+  if (maxlen >= (1ull << 32)) return fail(SS_EINVAL, "segments of 2^32 or more keys are not supported");
+  if (nseg >= (1ull << 31)) return fail(SS_EINVAL, "too many segments");
+  const uint32_t C = small_cap(ty.KW, ty.VW);
+  Layout L;
+  P->o_ctl = L.take(sizeof(Ctl));
+  P->o_small = L.take(sizeof(SmallEnt) * std::max<uint64_t>(nseg, 1));
+  P->s = prm.s;
+  const uint32_t p_cap = user_params ? std::min<uint32_t>(prm.p, 4096) : 256;
+  if (maxlen > C) {
+    P->o_tmp = L.take((size_t)ty.KW * total);
+    P->o_vtmp = ty.VW ? L.take((size_t)ty.VW * total) : 0;
+    uint64_t seg_cap0 = std::min<uint64_t>(nseg, total / (C + 1) + 1);
+    const bool recurse = !(prm.flags & SS_F_NO_RECURSION);
+    plan_levels(L, ty, total, seg_cap0, maxlen, 0, 0, 0, prm.s, p_cap, prm.tile, recurse, &P->lp);
+  }
+  P->bytes = L.cur;
+  return SS_OK;
+}
+
+template <int KW, int VW>
+struct Launch;
+
+// Bytes of an argument range, for overlap checks.
+bool overlap_partial(const void* a, size_t an, const void* b, size_t bn) {
+  if (!a || !b || !an || !bn) return false;
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  if (x == y && an == bn) return false;
+  return x < y + bn && y < x + an;
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void* vin, void* out, void* vout) {
+  const LevelPlan& lv = P.lp.lv[l];
+  LevelArgs a{};
+  Ctl* g = (Ctl*)(ws + P.o_ctl);
+  a.gctl = g;
+  a.segs = (SegDesc*)(ws + lv.o_segs);
+  a.ctl = &g->lv[l];
+  a.seg_cap = lv.seg_cap;
+  if (l + 1 < P.lp.nlev) {
+    a.next_segs = (SegDesc*)(ws + P.lp.lv[l + 1].o_segs);
+    a.next_ctl = &g->lv[l + 1];
+    a.next_cap = P.lp.lv[l + 1].seg_cap;
+  }
+  void* tmp = ws + P.o_tmp;
+  void* vtmp = P.ty.VW ? (void*)(ws + P.o_vtmp) : nullptr;
+  // level 0 reads the input and writes tmp; deeper levels alternate tmp <-> out
+  if (l == 0) {
+    a.src = in;
+    a.vsrc = P.ty.iota ? nullptr : vin;
+    a.dst = tmp;
+    a.vdst = vtmp;
+  } else if (l % 2 == 1) {
+    a.src = tmp;
+    a.vsrc = vtmp;
+    a.dst = out;
+    a.vdst = vout;
+  } else {
+    a.src = out;
+    a.vsrc = vout;
+    a.dst = tmp;
+    a.vdst = vtmp;
+  }
+  a.out = out;
+  a.vout = vout;
+  a.tmp = tmp;
+  a.vtmp = vtmp;
+  a.s_ord = ws + lv.o_sord;
+  a.s_tag = (uint32_t*)(ws + lv.o_stag);
+  if (l == 0 && P.lp.big_sample) {
+    a.s_ord2 = ws + P.lp.o_sord2;
+    a.s_tag2 = (uint32_t*)(ws + P.lp.o_stag2);
+  }
+  a.tree = ws + lv.o_tree;
+  a.tree_tag = lv.o_ttag ? (uint32_t*)(ws + lv.o_ttag) : nullptr;
+  a.hist = (uint32_t*)(ws + lv.o_hist);
+  a.scan_part = (uint32_t*)(ws + lv.o_part);
+  if (P.exp && l == 0) {
+    a.exp_smp_ord = (uint64_t*)(ws + P.o_exp_so);
+    a.exp_smp_tag = (uint64_t*)(ws + P.o_exp_st);
+    a.exp_spl_ord = (uint64_t*)(ws + P.o_exp_po);
+    a.exp_spl_tag = (uint64_t*)(ws + P.o_exp_pt);
+    a.exp_counts = (uint64_t*)(ws + P.o_exp_cnt);
+  }
+  a.tile = lv.tile;
+  a.s = lv.s;
+  a.p_cap = lv.p_cap;
+  a.target = lv.target;
+  a.kind = P.ty.kind;
+  a.iota = (l == 0 && P.ty.iota) ? 1 : 0;
+  return a;
+}
+
+uint32_t grid_of(uint64_t work, uint32_t per, uint32_t cap) {
+  uint64_t g = cdiv(std::max<uint64_t>(work, 1), per);
+  return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(g, 1), cap);
+}
+
+template <int KW, int VW>
+int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st) {
+  const uint32_t Cs = sample_cap(KW);
+  for (int l = 0; l < P.lp.nlev; l++) {
+    const LevelPlan& lv = P.lp.lv[l];
+    LevelArgs a = level_args(P, ws, l, in, vin, out, vout);
+    const int exp = (P.exp && l == 0) ? 1 : 0;
+    LAUNCH(PK_PLAN, k_plan, dim3(1), dim3(NT), 0, st, a, Cs);
+    LAUNCH_CHECK();
+    // sample
+    if (l == 0 && P.regular) {
+      const uint32_t S = P.s * P.p_eff;
+      LAUNCH(PK_SAMPLE, k_sample_regular<KW>, dim3(grid_of(P.m, 256, 4096)), dim3(256), 0, st, a,
+                         (const void*)(ws + P.o_regk), (const uint32_t*)(ws + P.o_regi), (uint64_t)P.n, P.p_eff, S);
+    } else {
+      LAUNCH(PK_SAMPLE, k_sample_random<KW>, dim3(grid_of(lv.samp_cap, 256, 4096)), dim3(256), 0, st, a);
+    }
+    LAUNCH_CHECK();
+    // sample sort and splitter tree
+    if (l == 0 && P.lp.big_sample) {
+      LAUNCH(PK_SAMPLE_SORT, k_sample_chunk_sort<KW>, dim3((uint32_t)cdiv(P.m, Cs)), dim3(NT), 0, st, a);
+      LAUNCH_CHECK();
+      void* so = a.s_ord;
+      uint32_t* stg = a.s_tag;
+      void* so2 = a.s_ord2;
+      uint32_t* st2 = a.s_tag2;
+      for (int ps = 0; ps < P.lp.merge_passes; ps++) {
+        uint32_t run = Cs << ps;
+        LAUNCH(PK_SAMPLE_MERGE, k_sample_merge<KW>, dim3((uint32_t)cdiv(P.m, MERGE_TILE)), dim3(NT), 0, st,
+                           (const void*)so, (const uint32_t*)stg, so2, st2, (uint32_t)P.m, run);
+        LAUNCH_CHECK();
+        std::swap(so, so2);
+        std::swap(stg, st2);
+      }
+      LAUNCH(PK_TREE, k_build_tree<KW>, dim3(grid_of(std::max<uint64_t>(P.m, P.p_eff), 256, 1024)), dim3(256), 0,
+                         st, a, (const void*)so, (const uint32_t*)stg, exp);
+    } else {
+      LAUNCH(PK_SAMPLE_SORT, k_sample_sort_wg<KW>, dim3(lv.seg_cap), dim3(NT), 0, st, a, exp);
+    }
+    LAUNCH_CHECK();
+    const uint32_t tiles = (uint32_t)lv.tiles_cap;
+    if (lv.pmax > 256) LAUNCH(PK_CLASSIFY, (k_classify<KW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
+    else LAUNCH(PK_CLASSIFY, (k_classify<KW, 256>), dim3(tiles), dim3(NT), 0, st, a);
+    LAUNCH_CHECK();
+    const uint32_t nb = (uint32_t)cdiv(std::max<uint64_t>(lv.hist_cap, 1), SCAN_BLOCK);
+    LAUNCH(PK_SCAN, k_scan_reduce, dim3(nb), dim3(NT), 0, st, a);
+    LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, a);
+    LAUNCH(PK_SCAN, k_scan_down, dim3(nb), dim3(NT), 0, st, a);
+    LAUNCH_CHECK();
+    if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
+    else LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 256>), dim3(tiles), dim3(NT), 0, st, a);
+    LAUNCH_CHECK();
+    LAUNCH(PK_BUCKET_SORT, (k_bucket_sort<KW, VW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a, exp);
+    LAUNCH_CHECK();
+  }
+  return SS_OK;
+}
+
+template <int KW, int VW>
+int run_segmented(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout,
+                  const int64_t* off, hipStream_t st) {
+  Ctl* g = (Ctl*)(ws + P.o_ctl);
+  const uint32_t C = small_cap(KW, VW);
+  LAUNCH(PK_INIT, k_init_ctl, dim3(1), dim3(64), 0, st, g);
+  LAUNCH_CHECK();
+  SegDesc* top = P.lp.nlev ? (SegDesc*)(ws + P.lp.lv[0].o_segs) : nullptr;
+  uint32_t top_cap = P.lp.nlev ? P.lp.lv[0].seg_cap : 0;
+  LAUNCH(PK_INIT, k_seg_init, dim3(grid_of(P.nseg, 256, 1024)), dim3(256), 0, st, g, off, (uint32_t)P.nseg,
+                     P.lp.nlev ? C : 0xFFFFFFFFu, top, top_cap, (SmallEnt*)(ws + P.o_small), P.prm.seed);
+  LAUNCH_CHECK();
+  LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)), dim3(NT), 0, st, g,
+                     (const SmallEnt*)(ws + P.o_small), in, vin, out, vout, P.ty.kind, P.ty.iota ? 1 : 0);
+  LAUNCH_CHECK();
+  return run_levels<KW, VW>(P, ws, in, vin, out, vout, st);
+}
+
+template <int KW, int VW>
+int run_single(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st) {
+  if (P.n == 0) return SS_OK;
+  Ctl* g = (Ctl*)(ws + P.o_ctl);
+  const void* vsrc = P.ty.iota ? nullptr : vin;
+  if (P.direct) {
+    LAUNCH(PK_INIT, k_init_ctl, dim3(1), dim3(64), 0, st, g);
+    LAUNCH(PK_SMALL_SORT, (k_sort_direct<KW, VW>), dim3(1), dim3(NT), 0, st, in, vsrc, out, vout, (uint64_t)0,
+                       (uint32_t)P.n, P.ty.kind);
+    LAUNCH_CHECK();
+    return SS_OK;
+  }
+  if (P.whole) {
+    LAUNCH(PK_INIT, k_init_ctl, dim3(1), dim3(64), 0, st, g);
+    LAUNCH(PK_SMALL_SORT, (k_sort_whole<KW, VW>), dim3(1), dim3(NT), 0, st, in, vsrc, out, vout,
+                       (void*)(ws + P.o_tmp), P.ty.VW ? (void*)(ws + P.o_vtmp) : nullptr, (uint64_t)P.n, P.ty.kind);
+    LAUNCH_CHECK();
+    return SS_OK;
+  }
+  if (P.regular) {
+    // Alg. 1 step 1: sort the p blocks (key, in-block index) with the segmented path
+    int64_t* boff = (int64_t*)(ws + P.o_regoff);
+    LAUNCH(PK_INIT, k_block_offsets, dim3(grid_of(P.p_eff + 1, 256, 64)), dim3(256), 0, st, boff, (uint64_t)P.n,
+                       P.p_eff);
+    LAUNCH_CHECK();
+    int rc = run_segmented<KW, 4>(*P.nested, ws + P.o_nested, in, nullptr, ws + P.o_regk, ws + P.o_regi, boff, st);
+    if (rc) return rc;
+  }
+  LAUNCH(PK_INIT, k_init_single, dim3(1), dim3(64), 0, st, g, (SegDesc*)(ws + P.lp.lv[0].o_segs), (uint64_t)P.n,
+                     P.p_eff, (uint32_t)P.m, P.stride, P.prm.seed);
+  LAUNCH_CHECK();
+  return run_levels<KW, VW>(P, ws, in, vin, out, vout, st);
+}
+
+template <int KW, int VW>
+int dispatch_single(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st) {
+  return run_single<KW, VW>(P, ws, in, vin, out, vout, st);
+}
+
+int run_single_any(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st) {
+  const int KW = P.ty.KW, VW = P.ty.VW;
+  if (KW == 4 && VW == 0) return dispatch_single<4, 0>(P, ws, in, vin, out, vout, st);
+  if (KW == 4 && VW == 4) return dispatch_single<4, 4>(P, ws, in, vin, out, vout, st);
+  if (KW == 4 && VW == 8) return dispatch_single<4, 8>(P, ws, in, vin, out, vout, st);
+  if (KW == 8 && VW == 0) return dispatch_single<8, 0>(P, ws, in, vin, out, vout, st);
+  if (KW == 8 && VW == 4) return dispatch_single<8, 4>(P, ws, in, vin, out, vout, st);
+  return dispatch_single<8, 8>(P, ws, in, vin, out, vout, st);
+}
+
+int run_segmented_any(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout,
+                      const int64_t* off, hipStream_t st) {
+  const int KW = P.ty.KW, VW = P.ty.VW;
+  if (KW == 4 && VW == 0) return run_segmented<4, 0>(P, ws, in, vin, out, vout, off, st);
+  if (KW == 4 && VW == 4) return run_segmented<4, 4>(P, ws, in, vin, out, vout, off, st);
+  if (KW == 4 && VW == 8) return run_segmented<4, 8>(P, ws, in, vin, out, vout, off, st);
+  if (KW == 8 && VW == 0) return run_segmented<8, 0>(P, ws, in, vin, out, vout, off, st);
+  if (KW == 8 && VW == 4) return run_segmented<8, 4>(P, ws, in, vin, out, vout, off, st);
+  return run_segmented<8, 8>(P, ws, in, vin, out, vout, off, st);
+}
+
+int check_ws(const Plan& P, const void* ws, size_t ws_bytes) {
+  if (P.bytes && !ws) return fail(SS_EWORKSPACE, "workspace is NULL (%zu bytes needed)", P.bytes);
+  if (ws_bytes < P.bytes) return fail(SS_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, P.bytes);
+  if (((uintptr_t)ws) % ALIGN) return fail(SS_EWORKSPACE, "workspace must be %zu-byte aligned", ALIGN);
+  return SS_OK;
+}
+
+int sort_common(const void* keys_in, const void* vals_in, void* keys_out, void* vals_out, size_t n, int key_type,
+                int val_type, const ss_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  Types ty;
+  int rc = parse_types(key_type, val_type, &ty);
+  if (rc) return rc;
+  ss_params p;
+  rc = check_params(prm, &p);
+  if (rc) return rc;
+  if (n == 0) return SS_OK;
+  if (!keys_in || !keys_out) return fail(SS_EINVAL, "keys_in and keys_out must be device pointers");
+  if (ty.VW) {
+    if (!vals_out) return fail(SS_EINVAL, "vals_out must be a device pointer");
+    if (ty.iota && vals_in) return fail(SS_EINVAL, "vals_in must be NULL for an IOTA payload");
+    if (!ty.iota && !vals_in) return fail(SS_EINVAL, "vals_in must be a device pointer");
+  }
+  const size_t kb = (size_t)ty.KW * n, vb = (size_t)ty.VW * n;
+  if (overlap_partial(keys_in, kb, keys_out, kb) || overlap_partial(vals_in, vb, vals_out, vb) ||
+      overlap_partial(keys_in, kb, vals_out, vb) || overlap_partial(vals_in, vb, keys_out, kb) ||
+      (keys_out == vals_out && ty.VW))
+    return fail(SS_EINVAL, "inputs and outputs overlap partially");
+  Plan P;
+  rc = plan_single(&P, n, ty, p);
+  if (rc) return rc;
+  rc = check_ws(P, ws, ws_bytes);
+  if (rc) return rc;
+  return run_single_any(P, (char*)ws, keys_in, vals_in, keys_out, vals_out, as_stream(stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ss_last_error(void) { return g_err; }
+
+int ss_workspace_size(size_t n, int key_type, int val_type, const ss_params* prm, size_t* bytes_out) {
+  g_err[0] = 0;
+  if (!bytes_out) return fail(SS_EINVAL, "bytes_out is NULL");
+  Types ty;
+  int rc = parse_types(key_type, val_type, &ty);
+  if (rc) return rc;
+  ss_params p;
+  rc = check_params(prm, &p);
+  if (rc) return rc;
+  Plan P;
+  rc = plan_single(&P, n, ty, p);
+  if (rc) return rc;
+  *bytes_out = P.bytes;
+  return SS_OK;
+}
+
+int ss_stage_layout(size_t n, int key_type, int val_type, const ss_params* prm, ss_stage_info* info) {
+  g_err[0] = 0;
+  if (!info) return fail(SS_EINVAL, "info is NULL");
+  Types ty;
+  int rc = parse_types(key_type, val_type, &ty);
+  if (rc) return rc;
+  ss_params p;
+  rc = check_params(prm, &p);
+  if (rc) return rc;
+  Plan P;
+  rc = plan_single(&P, n, ty, p);
+  if (rc) return rc;
+  memset(info, 0, sizeof *info);
+  info->p_eff = P.p_eff;
+  info->stride = P.stride;
+  info->m = P.m;
+  info->direct = (P.direct || P.whole) ? 1u : 0u;
+  info->levels = P.lp.nlev > 0 ? (uint32_t)(P.lp.nlev - 1) : 0u;
+  if (P.exp) {
+    info->sample_ord = P.o_exp_so;
+    info->sample_tag = P.o_exp_st;
+    info->spl_ord = P.o_exp_po;
+    info->spl_tag = P.o_exp_pt;
+    info->counts = P.o_exp_cnt;
+  }
+  return SS_OK;
+}
+
+int sample_sort_keys(const void* keys_in, void* keys_out, size_t n, int key_type, const ss_params* prm, void* ws,
+                     size_t ws_bytes, void* stream) {
+  return sort_common(keys_in, nullptr, keys_out, nullptr, n, key_type, SS_V_NONE, prm, ws, ws_bytes, stream);
+}
+
+int sample_sort_pairs(const void* keys_in, const void* vals_in, void* keys_out, void* vals_out, size_t n,
+                      int key_type, int val_type, const ss_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  if (val_type == SS_V_NONE) {
+    g_err[0] = 0;
+    return fail(SS_EINVAL, "sample_sort_pairs needs a payload type");
+  }
+  return sort_common(keys_in, vals_in, keys_out, vals_out, n, key_type, val_type, prm, ws, ws_bytes, stream);
+}
+
+int ss_segmented_workspace_size(size_t total, size_t num_segments, size_t max_seg_len, int key_type, int val_type,
+                                const ss_params* prm, size_t* bytes_out) {
+  g_err[0] = 0;
+  if (!bytes_out) return fail(SS_EINVAL, "bytes_out is NULL");
+  Types ty;
+  int rc = parse_types(key_type, val_type, &ty);
+  if (rc) return rc;
+  ss_params p;
+  rc = check_params(prm, &p);
+  if (rc) return rc;
+  Plan P;
+  rc = plan_segmented(&P, total, num_segments, max_seg_len, ty, p, prm != nullptr);
+  if (rc) return rc;
+  *bytes_out = P.bytes;
+  return SS_OK;
+}
+
+int segmented_sort(const void* keys_in, const void* vals_in, void* keys_out, void* vals_out, const int64_t* d_offsets,
+                   size_t num_segments, size_t total, size_t max_seg_len, int key_type, int val_type,
+                   const ss_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  Types ty;
+  int rc = parse_types(key_type, val_type, &ty);
+  if (rc) return rc;
+  ss_params p;
+  rc = check_params(prm, &p);
+  if (rc) return rc;
+  if (num_segments == 0 || total == 0) return SS_OK;
+  if (!keys_in || !keys_out || !d_offsets) return fail(SS_EINVAL, "keys and offsets must be device pointers");
+  if (ty.VW) {
+    if (!vals_out) return fail(SS_EINVAL, "vals_out must be a device pointer");
+    if (ty.iota && vals_in) return fail(SS_EINVAL, "vals_in must be NULL for an IOTA payload");
+    if (!ty.iota && !vals_in) return fail(SS_EINVAL, "vals_in must be a device pointer");
+  }
+  const size_t kb = (size_t)ty.KW * total, vb = (size_t)ty.VW * total;
+  if (overlap_partial(keys_in, kb, keys_out, kb) || overlap_partial(vals_in, vb, vals_out, vb) ||
+      overlap_partial(keys_in, kb, vals_out, vb) || overlap_partial(vals_in, vb, keys_out, kb))
+    return fail(SS_EINVAL, "inputs and outputs overlap partially");
+  Plan P;
+  rc = plan_segmented(&P, total, num_segments, max_seg_len, ty, p, prm != nullptr);
+  if (rc) return rc;
+  rc = check_ws(P, ws, ws_bytes);
+  if (rc) return rc;
+  return run_segmented_any(P, (char*)ws, keys_in, vals_in, keys_out, vals_out, d_offsets, as_stream(stream));
+}
+
+int ss_scatter_grad(const void* grad_y, const int64_t* perm, void* grad_x, size_t rows, size_t row_len,
+                    int elem_bytes, void* stream) {
+  g_err[0] = 0;
+  if (rows == 0 || row_len == 0) return SS_OK;
+  if (!grad_y || !perm || !grad_x) return fail(SS_EINVAL, "grad_y, perm and grad_x must be device pointers");
+  if (grad_y == grad_x) return fail(SS_EINVAL, "grad_x must not alias grad_y");
+  const uint64_t total = (uint64_t)rows * row_len;
+  const uint32_t grid = grid_of(total, 256, 8192);
+  hipStream_t st = as_stream(stream);
+  switch (elem_bytes) {
+    case 2:
+      LAUNCH(PK_GRAD, k_scatter_grad<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t*)grad_y, perm,
+                         (uint16_t*)grad_x, (uint64_t)rows, (uint64_t)row_len);
+      break;
+    case 4:
+      LAUNCH(PK_GRAD, k_scatter_grad<uint32_t>, dim3(grid), dim3(256), 0, st, (const uint32_t*)grad_y, perm,
+                         (uint32_t*)grad_x, (uint64_t)rows, (uint64_t)row_len);
+      break;
+    case 8:
+      LAUNCH(PK_GRAD, k_scatter_grad<uint64_t>, dim3(grid), dim3(256), 0, st, (const uint64_t*)grad_y, perm,
+                         (uint64_t*)grad_x, (uint64_t)rows, (uint64_t)row_len);
+      break;
+    default:
+      return fail(SS_EINVAL, "elem_bytes = %d: need 2, 4 or 8", elem_bytes);
+  }
+  LAUNCH_CHECK();
+  return SS_OK;
+}
+
+int ss_profile_enable(int on, int max_launches) {
+  g_err[0] = 0;
+  for (hipEvent_t e : g_prof.ev) hipEventDestroy(e);
+  g_prof = Prof();
+  if (!on) return SS_OK;
+  if (max_launches < 1 || max_launches > (1 << 20)) return fail(SS_EINVAL, "max_launches out of range");
+  g_prof.ev.resize(2 * (size_t)max_launches);
+  g_prof.kind.resize(max_launches);
+  for (auto& e : g_prof.ev) HIP_TRY(hipEventCreate(&e));
+  g_prof.cap = max_launches;
+  g_prof.on = true;
+  return SS_OK;
+}
+
+int ss_profile_collect(void) {
+  g_err[0] = 0;
+  for (int i = 0; i < g_prof.used; i++) {
+    HIP_TRY(hipEventSynchronize(g_prof.ev[2 * i + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]));
+    g_prof.total[g_prof.kind[i]] += ms;
+    g_prof.count[g_prof.kind[i]] += 1;
+  }
+  g_prof.used = 0;
+  return SS_OK;
+}
+
+int ss_profile_report(int kind, const char** name, double* total_ms, uint64_t* launches) {
+  if (kind < 0 || kind >= PK_COUNT) return SS_EINVAL;
+  if (name) *name = PROF_NAMES[kind];
+  if (total_ms) *total_ms = g_prof.total[kind];
+  if (launches) *launches = g_prof.count[kind];
+  return SS_OK;
+}
+
+int ss_status(const void* ws, void* stream) {
+  g_err[0] = 0;
+  if (!ws) return fail(SS_EINVAL, "ws is NULL");
+  HIP_TRY(hipStreamSynchronize(as_stream(stream)));
+  uint32_t st = 0;
+  HIP_TRY(hipMemcpy(&st, ws, sizeof st, hipMemcpyDeviceToHost));
+  if (st & ST_BAD_OFFSETS) return fail(SS_EDEVICE, "segment offsets decrease (status 0x%x)", st);
+  if (st) snprintf(g_err, sizeof g_err, "note: status 0x%x%s%s", st,
+                   (st & ST_FALLBACK) ? " (a bucket was sorted by the one-work-group fallback)" : "",
+                   (st & ST_LIST_FULL) ? " (a split-level list was full)" : "");
+  return SS_OK;
+}
+
+}  // extern "C"

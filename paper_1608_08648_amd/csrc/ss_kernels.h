@@ -1,0 +1,984 @@
+// Kernels of the oversampling sample sort (gfx950).
+//
+// One split level partitions a list of segments (each an independent sort
+// problem) into buckets:
+//   k_plan          per-segment bucket count p, sample size and offsets
+//   k_sample_*      draw the sample: random positions (Alg. 2 step 2) or the
+//                   regular order statistics of sorted blocks (Alg. 1 step 2)
+//   k_sample_sort_* sort the sample by (key, position), then lay the p-1
+//                   splitters (Alg. 1/2 step 3) out as an implicit search tree
+//   k_classify      count, per tile, the keys of each bucket (step 4)
+//   k_scan_*        exclusive scan of the bucket-major counts -> offsets
+//   k_scatter       stable split of the keys into their buckets (step 4)
+//   k_bucket_sort   sort every bucket in LDS; buckets too large for one
+//                   work-group go to the next level's list (or, past the
+//                   last planned level, to a one-work-group merge sort)
+// Keys are compared through their order-preserving unsigned image (ord);
+// ties are broken by the index inside the segment (Section 2.2's tags), so
+// every key is distinct for the split and the result is the stable order.
+#pragma once
+#include "ss_device.h"
+
+namespace ss {
+
+constexpr int NT = 512;          // threads per work-group (8 waves)
+constexpr int MAX_LEVELS = 6;    // split levels including the top one
+constexpr int SCAN_ITEMS = 8;    // scan: items per thread
+constexpr int SCAN_BLOCK = NT * SCAN_ITEMS;
+constexpr int MERGE_V = 4;       // merge: outputs per thread
+constexpr int MERGE_TILE = NT * MERGE_V;
+
+template <int KW> struct KeyOf;
+template <> struct KeyOf<4> { using T = uint32_t; };
+template <> struct KeyOf<8> { using T = uint64_t; };
+template <int VW> struct ValOf;
+template <> struct ValOf<0> { using T = NoVal; };
+template <> struct ValOf<4> { using T = uint32_t; };
+template <> struct ValOf<8> { using T = uint64_t; };
+
+// Items per thread of the one-work-group sort, by key and payload width;
+// NT * KMAX items fit in the 160 KB LDS of a CU.
+template <int KW, int VW> struct SmallCap {
+  static constexpr int KMAX = (KW + VW <= 4) ? 64 : ((KW + VW <= 8) ? 32 : 16);
+  static constexpr int C = NT * KMAX;
+};
+// Sample records (ord, tag): 4-byte keys pack into one u64.
+template <int KW> struct SampleCap {
+  static constexpr int KMAX = (KW == 4) ? 32 : 16;
+  static constexpr int C = NT * KMAX;
+};
+
+// Keys per thread in one chunk of the stable split.
+template <int KW, int VW> struct SplitChunk {
+  static constexpr int KS = (KW + VW <= 4) ? 8 : 4;
+  static constexpr int CH = NT * KS;
+};
+
+struct SegDesc {          // one sort problem at one split level
+  uint64_t beg;           // first element in the level's buffers
+  uint64_t seed;          // SplitMix64 state for its random sample
+  uint64_t hist_off;      // first entry of its bucket-major counts
+  uint32_t len;           // elements
+  uint32_t p;             // buckets (power of two; 0 = chosen by k_plan)
+  uint32_t lgp;
+  uint32_t m;             // sample records
+  uint32_t stride;        // splitter i = sample record i*stride - 1
+  uint32_t samp_off;      // first sample record
+  uint32_t tile_off;      // first tile (global tile index of the level)
+  uint32_t ntiles;
+  uint32_t bkt_off;       // first bucket (global bucket index of the level)
+  uint32_t tree_off;      // first tree slot (p slots, slot 0 unused)
+  uint32_t depth;         // split depth (0 = top)
+  uint32_t parent_bkt;    // bucket index inside the parent segment
+};
+
+struct LevelCtl {
+  uint32_t nsegs;
+  uint32_t total_samples;
+  uint32_t total_tiles;
+  uint32_t total_buckets;
+  uint64_t total_hist;
+  uint32_t total_tree;
+  uint32_t max_m;
+};
+
+struct SmallEnt { uint64_t beg; uint32_t len; uint32_t pad; };
+
+struct Ctl {              // device control block at the start of the workspace
+  uint32_t status;        // SS_ST_* bits
+  uint32_t nsmall;        // entries in the small-segment list
+  uint32_t pad[2];
+  LevelCtl lv[MAX_LEVELS];
+};
+
+enum : uint32_t {
+  ST_LIST_FULL = 1u,      // a next-level list was full (the bucket was sorted by the fallback)
+  ST_FALLBACK = 2u,       // a bucket larger than one work-group was sorted by the fallback
+  ST_BAD_OFFSETS = 4u,    // decreasing segment offsets (segment skipped)
+};
+
+// Everything one split level needs.
+struct LevelArgs {
+  SegDesc* segs;
+  LevelCtl* ctl;
+  SegDesc* next_segs;      // null at the last planned level
+  LevelCtl* next_ctl;
+  uint32_t next_cap;
+  uint32_t seg_cap;
+  Ctl* gctl;
+  const void* src;         // keys before the split
+  const void* vsrc;        // payload before the split (null if none / iota)
+  void* dst;               // keys after the split (bucketed)
+  void* vdst;
+  void* out;               // final output
+  void* vout;
+  void* tmp;               // workspace copy of the data (scratch for the fallback)
+  void* vtmp;
+  void* s_ord;             // sample key images (KW bytes each)
+  uint32_t* s_tag;         // sample tags
+  void* s_ord2;            // second sample buffer (merge passes)
+  uint32_t* s_tag2;
+  void* tree;              // splitter trees
+  uint32_t* tree_tag;      // tags of the tree (8-byte keys)
+  uint32_t* hist;          // counts, then offsets (in place)
+  uint32_t* scan_part;     // per-block partial sums of the scan
+  uint64_t* exp_smp_ord;   // stage export (top level), may be null
+  uint64_t* exp_smp_tag;
+  uint64_t* exp_spl_ord;
+  uint64_t* exp_spl_tag;
+  uint64_t* exp_counts;
+  uint32_t tile;           // keys per tile in the split passes
+  uint32_t s;              // oversampling factor for automatically sized segments
+  uint32_t p_cap;          // largest p for automatically sized segments
+  uint32_t target;         // aimed-at bucket size for automatically sized segments
+  int kind;                // 0 unsigned, 1 signed, 2 float
+  int iota;                // 1: payload = index in segment, generated (top level)
+};
+
+// ------------------------------------------------------------ helpers
+
+// index of the last segment whose field `off` is <= x (segments sorted by it)
+template <typename F>
+__device__ __forceinline__ uint32_t find_seg(const SegDesc* segs, uint32_t nsegs, uint64_t x, F off) {
+  uint32_t lo = 0, hi = nsegs;    // find first with off > x
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) / 2;
+    if (off(segs[mid]) <= x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo - 1;
+}
+
+// rank (1-based) among the p-1 splitters of Eytzinger slot k (tree of
+// depth lgp: slot 1 is the root, slots 2k and 2k+1 its children)
+__device__ __forceinline__ uint32_t eytz_rank(uint32_t k, uint32_t lgp) {
+  uint32_t d = 31 - __clz(k);
+  uint32_t i = k - (1u << d);
+  return (2 * i + 1) << (lgp - 1 - d);
+}
+
+__device__ __forceinline__ uint64_t derive_seed(uint64_t seed, uint32_t depth, uint32_t bucket) {
+  return sm64_mix(seed ^ sm64_mix(((uint64_t)depth << 32) + bucket));
+}
+
+// search tree in LDS: 4-byte keys as packed u64, 8-byte keys as (ord, tag)
+template <int KW, int PMAX>
+struct TreeLds;
+template <int PMAX>
+struct TreeLds<4, PMAX> {
+  uint64_t node[PMAX];
+  __device__ void load(const void* tree, const uint32_t*, uint32_t off, uint32_t p) {
+    const uint64_t* t = (const uint64_t*)tree + off;
+    for (uint32_t k = threadIdx.x; k < p; k += NT) node[k] = t[k];
+  }
+  // bucket = #{splitters < (ord, tag)}: walk lgp levels from the root
+  __device__ __forceinline__ uint32_t classify(uint32_t ord, uint32_t tag, uint32_t lgp, uint32_t p) const {
+    uint64_t e = ((uint64_t)ord << 32) | tag;
+    uint32_t k = 1;
+    for (uint32_t l = 0; l < lgp; l++) k = 2 * k + (node[k] < e ? 1u : 0u);
+    return k - p;
+  }
+};
+template <int PMAX>
+struct TreeLds<8, PMAX> {
+  uint64_t node[PMAX];
+  uint32_t tag[PMAX];
+  __device__ void load(const void* tree, const uint32_t* ttag, uint32_t off, uint32_t p) {
+    const uint64_t* t = (const uint64_t*)tree + off;
+    for (uint32_t k = threadIdx.x; k < p; k += NT) { node[k] = t[k]; tag[k] = ttag[off + k]; }
+  }
+  __device__ __forceinline__ uint32_t classify(uint64_t ord, uint32_t tg, uint32_t lgp, uint32_t p) const {
+    uint32_t k = 1;
+    for (uint32_t l = 0; l < lgp; l++) {
+      uint64_t a = node[k];
+      bool less = (a < ord) || (a == ord && tag[k] < tg);
+      k = 2 * k + (less ? 1u : 0u);
+    }
+    return k - p;
+  }
+};
+
+// ------------------------------------------------------- one-WG sort
+
+// LDS of the one-work-group sort of (key, payload) items.
+template <int KW, int VW, int KMAX>
+struct SmallLds {
+  using KT = typename KeyOf<KW>::T;
+  static constexpr int SLOTS = SortShape<NT, KMAX>::SLOTS;
+  uint32_t cnt[RadixLds<NT>::CNT_WORDS];
+  KT xh[SLOTS];
+  typename std::conditional<VW == 0, char, typename std::conditional<VW == 4, uint32_t, uint64_t>::type>::type
+      xv[VW == 0 ? 1 : SLOTS];
+  alignas(8) uint64_t red[64];
+};
+
+// Sort src[beg, beg+len) (len <= NT*K) into out[beg, beg+len).  The payload
+// comes from vsrc, or is the index inside the segment (iota_base + i) when
+// vsrc is null and the payload type is not NoVal.
+template <int KW, int VW, int K, int KMAX>
+__device__ __forceinline__ void sort_small_k(const typename KeyOf<KW>::T* src, const void* vsrc,
+                             typename KeyOf<KW>::T* out, void* vout, uint64_t beg, uint32_t len,
+                             uint64_t iota_base, int kind, SmallLds<KW, VW, KMAX>& sm) {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  constexpr bool HASV = VW != 0;
+  const int t = threadIdx.x;
+  VT* xv = (VT*)(void*)sm.xv;
+  // striped (coalesced) load into LDS, then blocked registers; a bounded
+  // unroll keeps the number of in-flight load addresses in check
+#pragma unroll 8
+  for (int r = 0; r < K; r++) {
+    int i = r * NT + t;
+    int j = pad_idx<K>(i);
+    if (i < (int)len) {
+      sm.xh[j] = to_ord(src[beg + i], kind);
+      if constexpr (HASV) {
+        if (vsrc) xv[j] = ((const VT*)vsrc)[beg + i];
+        else xv[j] = (VT)(iota_base + i);
+      }
+    } else {
+      sm.xh[j] = ~KT(0);
+    }
+  }
+  __syncthreads();
+  KT hi[K];
+  uint32_t lo[K];
+  VT val[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    int j = pad_idx<K>(t * K + k);
+    hi[k] = sm.xh[j];
+    if constexpr (HASV) val[k] = xv[j];
+  }
+  // (the sort's first LDS exchange comes after its internal barriers)
+  block_radix_sort<NT, K, KT, false, VT>(hi, lo, val, (int)len, sm.cnt, sm.xh, nullptr, xv, sm.red);
+#pragma unroll 8
+  for (int r = 0; r < K; r++) {
+    int i = r * NT + t;
+    if (i < (int)len) {
+      int j = pad_idx<K>(i);
+      out[beg + i] = from_ord(sm.xh[j], kind);
+      if constexpr (HASV) ((VT*)vout)[beg + i] = xv[j];
+    }
+  }
+  __syncthreads();
+}
+
+template <int KW, int VW>
+__device__ __forceinline__ void sort_small(const typename KeyOf<KW>::T* src, const void* vsrc, typename KeyOf<KW>::T* out,
+                           void* vout, uint64_t beg, uint32_t len, uint64_t iota_base, int kind,
+                           SmallLds<KW, VW, SmallCap<KW, VW>::KMAX>& sm) {
+  constexpr int KMAX = SmallCap<KW, VW>::KMAX;
+  if (len <= (uint32_t)NT * 1) sort_small_k<KW, VW, 1, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kind, sm);
+  else if (len <= (uint32_t)NT * 4) sort_small_k<KW, VW, 4, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kind, sm);
+  else if (len <= (uint32_t)NT * 16) sort_small_k<KW, VW, 16, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kind, sm);
+  else sort_small_k<KW, VW, KMAX, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kind, sm);
+}
+
+// One work-group sorts a segment of any length: LDS-sorted chunks of C
+// items, then stable two-way merges (merge path) through global memory,
+// alternating between `out` and `alt`, ending in `out`.  `cur` holds the
+// data (it may be `out` or `alt`).
+template <int KW, int VW>
+__device__ void sort_big_wg(const typename KeyOf<KW>::T* cur, const void* vcur, typename KeyOf<KW>::T* out,
+                            void* vout, typename KeyOf<KW>::T* alt, void* valt, uint64_t beg, uint64_t len,
+                            uint64_t iota_base, int kind, SmallLds<KW, VW, SmallCap<KW, VW>::KMAX>& sm) {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  constexpr bool HASV = VW != 0;
+  constexpr uint64_t C = SmallCap<KW, VW>::C;
+  uint64_t nch = (len + C - 1) / C;
+  int passes = 0;
+  while ((C << passes) < len) passes++;
+  // the merges alternate buffers; pick the chunk-sort target so the last lands in out
+  KT* b0 = (passes % 2 == 0) ? out : alt;
+  void* vb0 = (passes % 2 == 0) ? vout : valt;
+  KT* b1 = (passes % 2 == 0) ? alt : out;
+  void* vb1 = (passes % 2 == 0) ? valt : vout;
+  for (uint64_t c = 0; c < nch; c++) {
+    uint64_t cb = c * C;
+    uint32_t cl = (uint32_t)((len - cb) < C ? (len - cb) : C);
+    sort_small<KW, VW>(cur, vcur, b0, vb0, beg + cb, cl, iota_base + cb, kind, sm);
+  }
+  if (passes == 0) return;
+  __threadfence_block();
+  for (int ps = 0; ps < passes; ps++) {
+    __syncthreads();
+    uint64_t run = C << ps;
+    const KT* a = b0;
+    const VT* va = (const VT*)vb0;
+    KT* o = b1;
+    VT* vo = (VT*)vb1;
+    for (uint64_t pb = 0; pb < len; pb += 2 * run) {
+      uint64_t la = (len - pb) < run ? (len - pb) : run;
+      uint64_t lb = (len - pb - la) < run ? (len - pb - la) : run;
+      const KT* A = a + beg + pb;
+      const KT* B = A + la;
+      uint64_t tot = la + lb;
+      for (uint64_t d0 = 0; d0 < tot; d0 += (uint64_t)NT * MERGE_V) {
+        uint64_t d = d0 + (uint64_t)threadIdx.x * MERGE_V;
+        if (d < tot) {
+          auto ga = [&](uint64_t i) { return to_ord(A[i], kind); };
+          auto gb = [&](uint64_t i) { return to_ord(B[i], kind); };
+          uint64_t i = merge_path(d, la, lb, ga, gb, [](KT x, KT y) { return x <= y; });
+          uint64_t j = d - i;
+          for (int v = 0; v < MERGE_V && d + v < tot; v++) {
+            bool takeA;
+            if (i >= la) takeA = false;
+            else if (j >= lb) takeA = true;
+            else takeA = to_ord(A[i], kind) <= to_ord(B[j], kind);
+            uint64_t dst = beg + pb + d + v;
+            if (takeA) {
+              o[dst] = A[i];
+              if constexpr (HASV) vo[dst] = va[beg + pb + i];
+              i++;
+            } else {
+              o[dst] = B[j];
+              if constexpr (HASV) vo[dst] = va[beg + pb + la + j];
+              j++;
+            }
+          }
+        }
+      }
+    }
+    __threadfence_block();
+    // swap roles
+    KT* tk = b0; b0 = b1; b1 = tk;
+    void* tv = vb0; vb0 = vb1; vb1 = tv;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ kernels
+
+// Per segment: bucket count, sample size, tile count and prefix offsets.
+// One work-group.  Segments with p == 0 are sized here from their length:
+// enough buckets for about `target` keys each (at most p_cap), and an
+// oversampling factor cut so that p*s < len/2 (Claim 1's precondition) and
+// the sample fits one work-group.
+__global__ void __launch_bounds__(NT) k_plan(LevelArgs a, uint32_t samp_cap) {
+  __shared__ uint64_t sh64[NT / WAVE + 2];
+  __shared__ uint32_t sh32[NT / WAVE + 2];
+  const uint32_t n = min(a.ctl->nsegs, a.seg_cap);
+  uint32_t run_s = 0, run_t = 0, run_b = 0, max_m = 0;
+  uint64_t run_h = 0;
+  for (uint32_t base = 0; base < n; base += NT) {
+    const uint32_t i = base + threadIdx.x;
+    uint32_t m = 0, nt = 0, p = 0;
+    uint64_t h = 0;
+    SegDesc d = {};
+    if (i < n) {
+      d = a.segs[i];
+      if (d.p == 0) {
+        uint32_t want = (d.len + a.target - 1) / a.target;
+        uint32_t q = 2;
+        while (q < want && q < a.p_cap) q *= 2;
+        uint32_t sv = a.s;
+        if ((uint64_t)q * sv > (uint64_t)samp_cap + 1) sv = (samp_cap + 1) / q;
+        if ((uint64_t)2 * q * sv >= d.len) sv = (d.len - 1) / (2 * q);
+        if (sv < 1) sv = 1;
+        d.p = q;
+        d.m = q * sv - 1;
+        d.stride = sv;
+      }
+      d.lgp = 31 - __clz(d.p);
+      d.ntiles = (d.len + a.tile - 1) / a.tile;
+      m = d.m;
+      nt = d.ntiles;
+      p = d.p;
+      h = (uint64_t)p * nt;
+    }
+    uint32_t ts, tt, tb;
+    uint64_t th;
+    const uint32_t so = block_excl_scan<NT>(m, sh32, &ts);
+    const uint32_t to = block_excl_scan<NT>(nt, sh32, &tt);
+    const uint32_t bo = block_excl_scan<NT>(p, sh32, &tb);
+    const uint64_t ho = block_excl_scan<NT, uint64_t>(h, sh64, &th);
+    const uint32_t wm = wave_max(m);
+    if (lane_id() == 0) sh32[wave_id()] = wm;
+    __syncthreads();
+    for (int w = 0; w < NT / WAVE; w++) max_m = sh32[w] > max_m ? sh32[w] : max_m;
+    __syncthreads();
+    if (i < n) {
+      d.samp_off = run_s + so;
+      d.tile_off = run_t + to;
+      d.bkt_off = run_b + bo;
+      d.tree_off = run_b + bo;
+      d.hist_off = run_h + ho;
+      a.segs[i] = d;
+    }
+    run_s += ts;
+    run_t += tt;
+    run_b += tb;
+    run_h += th;
+  }
+  if (threadIdx.x == 0) {
+    a.ctl->nsegs = n;
+    a.ctl->total_samples = run_s;
+    a.ctl->total_tiles = run_t;
+    a.ctl->total_buckets = run_b;
+    a.ctl->total_tree = run_b;
+    a.ctl->total_hist = run_h;
+    a.ctl->max_m = max_m;
+  }
+}
+
+// Random sample (Alg. 2 step 2): record j of segment g is the key at
+// in-segment position floor(r_j * len / 2^64), r_j the (j+1)-th output of
+// the segment's SplitMix64 generator; tag = that position.
+template <int KW>
+__global__ void __launch_bounds__(256) k_sample_random(LevelArgs a) {
+  using KT = typename KeyOf<KW>::T;
+  const uint32_t total = a.ctl->total_samples, nsegs = a.ctl->nsegs;
+  for (uint32_t g = blockIdx.x * 256 + threadIdx.x; g < total; g += gridDim.x * 256) {
+    uint32_t si = find_seg(a.segs, nsegs, g, [](const SegDesc& d) { return (uint64_t)d.samp_off; });
+    SegDesc d = a.segs[si];
+    uint32_t j = g - d.samp_off;
+    uint64_t pos = scale_to(sm64_at(d.seed, j), d.len);
+    KT key = to_ord(((const KT*)a.src)[d.beg + pos], a.kind);
+    ((KT*)a.s_ord)[g] = key;
+    a.s_tag[g] = (uint32_t)pos;
+  }
+}
+
+// LDS of the one-work-group sample sort.
+template <int KW>
+struct SampleLds {
+  static constexpr int KMAX = SampleCap<KW>::KMAX;
+  static constexpr int SLOTS = SortShape<NT, KMAX>::SLOTS;
+  uint32_t cnt[RadixLds<NT>::CNT_WORDS];
+  uint64_t xh[SLOTS];
+  uint32_t xl[KW == 8 ? SLOTS : 1];
+  alignas(8) uint64_t red[64];
+};
+
+// Write splitter tree slot k from sorted record (ord, tag), and export.
+template <int KW>
+__device__ __forceinline__ void put_tree(const LevelArgs& a, const SegDesc& d, uint32_t k,
+                                         typename KeyOf<KW>::T ord, uint32_t tag, bool exp) {
+  if constexpr (KW == 4) ((uint64_t*)a.tree)[d.tree_off + k] = ((uint64_t)ord << 32) | tag;
+  else {
+    ((uint64_t*)a.tree)[d.tree_off + k] = ord;
+    a.tree_tag[d.tree_off + k] = tag;
+  }
+  if (exp) {
+    uint32_t r = eytz_rank(k, d.lgp);
+    a.exp_spl_ord[r - 1] = (uint64_t)ord;
+    a.exp_spl_tag[r - 1] = tag;
+  }
+}
+
+// One work-group per segment: sort its sample (m <= SampleCap) by (key,
+// tag) in LDS, then write the splitter tree: splitter i = sorted record
+// i*stride - 1 (1-based i, Alg. 1/2 step 3).
+template <int KW, int K>
+__device__ __forceinline__ void sample_sort_one(const LevelArgs& a, const SegDesc& d, SampleLds<KW>& sm, bool exp) {
+  using KT = typename KeyOf<KW>::T;
+  constexpr int KM = SampleLds<KW>::KMAX;
+  const int t = threadIdx.x;
+  const KT* so = (const KT*)a.s_ord + d.samp_off;
+  const uint32_t* st = a.s_tag + d.samp_off;
+  const int m = (int)d.m;
+  uint64_t hi[K];
+  uint32_t lo[K];
+  NoVal nv[K];
+  // striped load to LDS then blocked registers
+#pragma unroll
+  for (int r = 0; r < K; r++) {
+    int i = r * NT + t;
+    int j = pad_idx<K>(i);
+    if (i < m) {
+      if constexpr (KW == 4) sm.xh[j] = ((uint64_t)so[i] << 32) | st[i];
+      else { sm.xh[j] = so[i]; sm.xl[j] = st[i]; }
+    } else {
+      sm.xh[j] = ~0ull;
+      if constexpr (KW == 8) sm.xl[j] = ~0u;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    int j = pad_idx<K>(t * K + k);
+    hi[k] = sm.xh[j];
+    if constexpr (KW == 8) lo[k] = sm.xl[j];
+  }
+  block_radix_sort<NT, K, uint64_t, KW == 8, NoVal>(hi, lo, nv, m, sm.cnt, sm.xh, sm.xl, nullptr, sm.red);
+  (void)KM;
+  // sorted records back to global (kept for the stage export)
+  for (int i = t; i < m; i += NT) {
+    int j = pad_idx<K>(i);
+    KT ord;
+    uint32_t tag;
+    if constexpr (KW == 4) { ord = (KT)(sm.xh[j] >> 32); tag = (uint32_t)sm.xh[j]; }
+    else { ord = sm.xh[j]; tag = sm.xl[j]; }
+    ((KT*)a.s_ord)[d.samp_off + i] = ord;
+    a.s_tag[d.samp_off + i] = tag;
+    if (exp) { a.exp_smp_ord[i] = (uint64_t)ord; a.exp_smp_tag[i] = tag; }
+  }
+  for (uint32_t k = 1 + t; k < d.p; k += NT) {
+    uint32_t r = eytz_rank(k, d.lgp);
+    int j = pad_idx<K>((int)(r * d.stride - 1));
+    KT ord;
+    uint32_t tag;
+    if constexpr (KW == 4) { ord = (KT)(sm.xh[j] >> 32); tag = (uint32_t)sm.xh[j]; }
+    else { ord = sm.xh[j]; tag = sm.xl[j]; }
+    put_tree<KW>(a, d, k, ord, tag, exp);
+  }
+  __syncthreads();
+}
+
+template <int KW>
+__global__ void __launch_bounds__(NT) k_sample_sort_wg(LevelArgs a, int export_stages) {
+  __shared__ SampleLds<KW> sm;
+  const uint32_t g = blockIdx.x;
+  if (g >= a.ctl->nsegs) return;
+  SegDesc d = a.segs[g];
+  constexpr int KM = SampleLds<KW>::KMAX;
+  if (d.m > (uint32_t)NT * KM) return;  // sorted by the multi-work-group path
+  bool exp = export_stages && d.depth == 0 && g == 0;
+  if (d.m <= (uint32_t)NT) sample_sort_one<KW, 1>(a, d, sm, exp);
+  else if (d.m <= (uint32_t)NT * 4) sample_sort_one<KW, 4>(a, d, sm, exp);
+  else if (d.m <= (uint32_t)NT * 16) sample_sort_one<KW, 16>(a, d, sm, exp);
+  else sample_sort_one<KW, KM>(a, d, sm, exp);
+}
+
+// Large top-level sample (one segment): chunk sorts, merges, tree.
+template <int KW>
+__global__ void __launch_bounds__(NT) k_sample_chunk_sort(LevelArgs a) {
+  __shared__ SampleLds<KW> sm;
+  using KT = typename KeyOf<KW>::T;
+  constexpr int KM = SampleLds<KW>::KMAX;
+  constexpr int C = NT * KM;
+  SegDesc d = a.segs[0];
+  uint32_t cb = blockIdx.x * C;
+  if (cb >= d.m) return;
+  SegDesc dc = d;
+  dc.samp_off = d.samp_off + cb;
+  dc.m = (d.m - cb) < (uint32_t)C ? (d.m - cb) : (uint32_t)C;
+  dc.p = 1;  // no tree from a chunk
+  sample_sort_one<KW, KM>(a, dc, sm, false);
+  (void)sizeof(KT);
+}
+
+// Stable merge of sorted runs of length `run` of the sample: (ord, tag) records.
+template <int KW>
+__global__ void __launch_bounds__(NT) k_sample_merge(const void* sord, const uint32_t* stag, void* dord,
+                                                     uint32_t* dtag, uint32_t m, uint32_t run) {
+  using KT = typename KeyOf<KW>::T;
+  const KT* so = (const KT*)sord;
+  KT* dk = (KT*)dord;
+  uint64_t o0 = (uint64_t)blockIdx.x * MERGE_TILE;
+  if (o0 >= m) return;
+  uint64_t pb = (o0 / (2ull * run)) * (2ull * run);
+  uint64_t la = (m - pb) < run ? (m - pb) : run;
+  uint64_t lb = (m - pb - la) < run ? (m - pb - la) : run;
+  uint64_t tot = la + lb;
+  uint64_t d = o0 - pb + (uint64_t)threadIdx.x * MERGE_V;
+  if (d >= tot) return;
+  auto less = [](KT ak, uint32_t at, KT bk, uint32_t bt) { return ak < bk || (ak == bk && at < bt); };
+  const KT* A = so + pb;
+  const uint32_t* At = stag + pb;
+  const KT* B = A + la;
+  const uint32_t* Bt = At + la;
+  uint64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) / 2;
+    uint64_t bj = d - 1 - mid;
+    if (!less(B[bj], Bt[bj], A[mid], At[mid])) lo = mid + 1;  // A[mid] <= B[bj]
+    else hi = mid;
+  }
+  uint64_t i = lo, j = d - lo;
+  for (int v = 0; v < MERGE_V && d + v < tot; v++) {
+    bool takeA;
+    if (i >= la) takeA = false;
+    else if (j >= lb) takeA = true;
+    else takeA = !less(B[j], Bt[j], A[i], At[i]);
+    uint64_t o = pb + d + v;
+    if (takeA) { dk[o] = A[i]; dtag[o] = At[i]; i++; }
+    else { dk[o] = B[j]; dtag[o] = Bt[j]; j++; }
+  }
+}
+
+// Splitter tree (and stage export) from a sorted sample in global memory.
+template <int KW>
+__global__ void __launch_bounds__(256) k_build_tree(LevelArgs a, const void* sord, const uint32_t* stag,
+                                                    int export_stages) {
+  using KT = typename KeyOf<KW>::T;
+  SegDesc d = a.segs[0];
+  bool exp = export_stages != 0;
+  const KT* so = (const KT*)sord;
+  uint32_t gid = blockIdx.x * 256 + threadIdx.x;
+  for (uint32_t k = gid; k < d.p; k += gridDim.x * 256) {
+    if (k == 0) continue;
+    uint32_t r = eytz_rank(k, d.lgp);
+    uint32_t idx = d.samp_off + r * d.stride - 1;
+    put_tree<KW>(a, d, k, so[idx], stag[idx], exp);
+  }
+  if (exp) {
+    for (uint32_t i = gid; i < d.m; i += gridDim.x * 256) {
+      a.exp_smp_ord[i] = (uint64_t)so[d.samp_off + i];
+      a.exp_smp_tag[i] = stag[d.samp_off + i];
+    }
+  }
+}
+
+// Regular sample (Alg. 1 steps 1-2) from blocks already sorted by (key,
+// in-block index): block k = [floor(k n/p), floor((k+1) n/p)); with
+// S = s*p and x = ceil(ceil(n/p)/S), record j of block k is the block's
+// record of rank min((j+1) x, |block|) - 1; tag = input position.
+template <int KW>
+__global__ void __launch_bounds__(256) k_sample_regular(LevelArgs a, const void* skeys, const uint32_t* sidx,
+                                                        uint64_t n, uint32_t p, uint32_t S) {
+  using KT = typename KeyOf<KW>::T;
+  const uint64_t total = (uint64_t)p * S;
+  const uint64_t blk_max = (n + p - 1) / p;
+  const uint64_t x = (blk_max + S - 1) / S;
+  for (uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x; g < total; g += (uint64_t)gridDim.x * 256) {
+    uint64_t k = g / S, j = g % S;
+    uint64_t b = (k * n) / p, e = ((k + 1) * n) / p, mk = e - b;
+    uint64_t rank = (j + 1) * x;
+    if (rank > mk) rank = mk;
+    uint64_t at = b + rank - 1;
+    ((KT*)a.s_ord)[g] = to_ord(((const KT*)skeys)[at], a.kind);
+    a.s_tag[g] = (uint32_t)(b + sidx[at]);
+  }
+}
+
+// Per-tile bucket counts (step 4), stored bucket-major per segment:
+// hist[hist_off + b * ntiles + tile].
+template <int KW, int PMAX>
+__global__ void __launch_bounds__(NT) k_classify(LevelArgs a) {
+  using KT = typename KeyOf<KW>::T;
+  __shared__ TreeLds<KW, PMAX> tr;
+  __shared__ uint32_t cnt[PMAX];
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const LevelCtl c = *a.ctl;
+  if (tile >= c.total_tiles) return;
+  const uint32_t si = find_seg(a.segs, c.nsegs, tile, [](const SegDesc& d) { return (uint64_t)d.tile_off; });
+  const SegDesc d = a.segs[si];
+  const uint32_t tw = tile - d.tile_off;
+  tr.load(a.tree, a.tree_tag, d.tree_off, d.p);
+  for (uint32_t b = threadIdx.x; b < d.p; b += NT) cnt[b] = 0;
+  __syncthreads();
+  const uint32_t t0 = tw * a.tile;
+  const uint32_t t1 = min(t0 + a.tile, d.len);
+  const KT* src = (const KT*)a.src + d.beg;
+  uint32_t cur = ~0u, run = 0;
+  for (uint32_t i = t0 + threadIdx.x; i < t1; i += NT) {
+    KT key = to_ord(src[i], a.kind);
+    uint32_t b = tr.classify(key, i, d.lgp, d.p);
+    if (b != cur) {
+      if (run) atomicAdd(&cnt[cur], run);
+      cur = b;
+      run = 0;
+    }
+    run++;
+  }
+  if (run) atomicAdd(&cnt[cur], run);
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < d.p; b += NT) a.hist[d.hist_off + (uint64_t)b * d.ntiles + tw] = cnt[b];
+}
+
+// Exclusive scan of the level's counts (u32, wrapping mod 2^32; only
+// differences inside one segment are used, and those are < 2^32).
+__global__ void __launch_bounds__(NT) k_scan_reduce(LevelArgs a) {
+  __shared__ uint32_t sh[NT / WAVE + 2];
+  const uint64_t total = a.ctl->total_hist;
+  uint64_t b0 = (uint64_t)blockIdx.x * SCAN_BLOCK;
+  if (b0 >= total) return;
+  uint32_t s = 0;
+  for (int r = 0; r < SCAN_ITEMS; r++) {
+    uint64_t i = b0 + (uint64_t)r * NT + threadIdx.x;
+    if (i < total) s += a.hist[i];
+  }
+  uint32_t tot;
+  block_excl_scan<NT>(s, sh, &tot);
+  if (threadIdx.x == 0) a.scan_part[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(NT) k_scan_partials(LevelArgs a) {
+  __shared__ uint32_t sh[NT / WAVE + 2];
+  const uint64_t total = a.ctl->total_hist;
+  const uint32_t nb = (uint32_t)((total + SCAN_BLOCK - 1) / SCAN_BLOCK);
+  uint32_t run = 0;
+  for (uint32_t base = 0; base < nb; base += NT) {
+    uint32_t i = base + threadIdx.x;
+    uint32_t v = i < nb ? a.scan_part[i] : 0;
+    uint32_t tot;
+    uint32_t e = block_excl_scan<NT>(v, sh, &tot);
+    if (i < nb) a.scan_part[i] = run + e;
+    run += tot;
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_scan_down(LevelArgs a) {
+  __shared__ uint32_t sh[NT / WAVE + 2];
+  const uint64_t total = a.ctl->total_hist;
+  uint64_t b0 = (uint64_t)blockIdx.x * SCAN_BLOCK;
+  if (b0 >= total) return;
+  // thread t owns the SCAN_ITEMS consecutive entries starting at b0 + t*SCAN_ITEMS
+  uint32_t v[SCAN_ITEMS];
+  uint32_t s = 0;
+  for (int k = 0; k < SCAN_ITEMS; k++) {
+    uint64_t i = b0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
+    v[k] = i < total ? a.hist[i] : 0;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan<NT>(s, sh, &tot) + a.scan_part[blockIdx.x];
+  for (int k = 0; k < SCAN_ITEMS; k++) {
+    uint64_t i = b0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
+    if (i < total) a.hist[i] = run;
+    run += v[k];
+  }
+}
+
+// Stable split (step 4): every key moves to its bucket, keeping input order
+// inside each (tile, bucket); tiles keep their order through the offsets.
+template <int KW, int VW, int PMAX>
+struct ScatterLds {
+  using KT = typename KeyOf<KW>::T;
+  static constexpr int KS = SplitChunk<KW, VW>::KS;
+  static constexpr int CH = SplitChunk<KW, VW>::CH;
+  static constexpr int SLOTS = SortShape<NT, KS>::SLOTS;
+  TreeLds<KW, PMAX> tr;
+  uint32_t gofs[PMAX];   // next free in-segment position of each bucket
+  uint32_t adj[PMAX];    // gofs - first sorted index of the bucket in the chunk
+  uint32_t cnt[RadixLds<NT>::CNT_WORDS];
+  uint32_t xw[SLOTS];    // (bucket << 16 | chunk index), sorted by bucket
+  KT ck[SLOTS];          // the chunk's keys (raw)
+  typename std::conditional<VW == 0, char, typename std::conditional<VW == 4, uint32_t, uint64_t>::type>::type
+      cv[VW == 0 ? 1 : SLOTS];
+  alignas(8) uint64_t red[64];
+};
+
+template <int KW, int VW, int PMAX>
+__global__ void __launch_bounds__(NT) k_scatter(LevelArgs a) {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  using L = ScatterLds<KW, VW, PMAX>;
+  constexpr int KS = L::KS;
+  constexpr int CH = L::CH;
+  constexpr bool HASV = VW != 0;
+  __shared__ L sm;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const LevelCtl c = *a.ctl;
+  if (tile >= c.total_tiles) return;
+  const uint32_t si = find_seg(a.segs, c.nsegs, tile, [](const SegDesc& d) { return (uint64_t)d.tile_off; });
+  const SegDesc d = a.segs[si];
+  const uint32_t tw = tile - d.tile_off;
+  const int t = threadIdx.x;
+  sm.tr.load(a.tree, a.tree_tag, d.tree_off, d.p);
+  const uint32_t base = a.hist[d.hist_off];
+  for (uint32_t b = t; b < d.p; b += NT) sm.gofs[b] = a.hist[d.hist_off + (uint64_t)b * d.ntiles + tw] - base;
+  __syncthreads();
+  const uint32_t t0 = tw * a.tile;
+  const uint32_t t1 = min(t0 + a.tile, d.len);
+  const KT* src = (const KT*)a.src + d.beg;
+  const VT* vsrc = (const VT*)a.vsrc;
+  KT* dst = (KT*)a.dst + d.beg;
+  VT* vdst = (VT*)a.vdst;
+  VT* cv = (VT*)(void*)sm.cv;
+  for (uint32_t c0 = t0; c0 < t1; c0 += CH) {
+    const int cn = (int)min((uint32_t)CH, t1 - c0);
+    // striped load of the chunk
+#pragma unroll
+    for (int r = 0; r < KS; r++) {
+      int i = r * NT + t;
+      if (i < cn) {
+        int j = pad_idx<KS>(i);
+        sm.ck[j] = src[c0 + i];
+        if constexpr (HASV) {
+          if (a.iota) cv[j] = (VT)(c0 + i);
+          else cv[j] = vsrc[d.beg + c0 + i];
+        }
+      }
+    }
+    __syncthreads();
+    // classify blocked items, pack (bucket, chunk index)
+    uint32_t w[KS];
+    uint32_t lo[KS];
+    NoVal nv[KS];
+#pragma unroll
+    for (int k = 0; k < KS; k++) {
+      int i = t * KS + k;
+      if (i < cn) {
+        KT key = to_ord(sm.ck[pad_idx<KS>(i)], a.kind);
+        uint32_t b = sm.tr.classify(key, c0 + i, d.lgp, d.p);
+        w[k] = (b << 16) | (uint32_t)i;
+      } else {
+        w[k] = ~0u;
+      }
+    }
+    block_radix_sort<NT, KS, uint32_t, false, NoVal>(w, lo, nv, cn, sm.cnt, sm.xw, nullptr, nullptr, sm.red, 16);
+    // first element of each bucket's run
+    for (int j = t; j < cn; j += NT) {
+      uint32_t b = sm.xw[pad_idx<KS>(j)] >> 16;
+      uint32_t pb = j ? (sm.xw[pad_idx<KS>(j - 1)] >> 16) : ~0u;
+      if (b != pb) sm.adj[b] = sm.gofs[b] - (uint32_t)j;
+    }
+    __syncthreads();
+    for (int j = t; j < cn; j += NT) {
+      uint32_t wv = sm.xw[pad_idx<KS>(j)];
+      uint32_t b = wv >> 16, i = wv & 0xFFFFu;
+      uint32_t pos = sm.adj[b] + (uint32_t)j;
+      dst[pos] = sm.ck[pad_idx<KS>(i)];
+      if constexpr (HASV) vdst[d.beg + pos] = cv[pad_idx<KS>(i)];
+      uint32_t nb = (j + 1 < cn) ? (sm.xw[pad_idx<KS>(j + 1)] >> 16) : ~0u;
+      if (b != nb) sm.gofs[b] = pos + 1;
+    }
+    __syncthreads();
+  }
+}
+
+// Buckets of the level: sort in LDS, or hand to the next level / fallback.
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_bucket_sort(LevelArgs a, int export_stages) {
+  using KT = typename KeyOf<KW>::T;
+  constexpr int KMAX = SmallCap<KW, VW>::KMAX;
+  constexpr uint32_t C = SmallCap<KW, VW>::C;
+  __shared__ SmallLds<KW, VW, KMAX> sm;
+  const LevelCtl c = *a.ctl;
+  const uint32_t x = blockIdx.x;
+  if (x >= c.total_buckets) return;
+  const uint32_t si = find_seg(a.segs, c.nsegs, x, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
+  const SegDesc d = a.segs[si];
+  const uint32_t b = x - d.bkt_off;
+  const uint32_t base = a.hist[d.hist_off];
+  const uint32_t st = a.hist[d.hist_off + (uint64_t)b * d.ntiles] - base;
+  const uint32_t en = (b + 1 < d.p) ? a.hist[d.hist_off + (uint64_t)(b + 1) * d.ntiles] - base : d.len;
+  const uint32_t sz = en - st;
+  if (export_stages && d.depth == 0 && si == 0 && threadIdx.x == 0) a.exp_counts[b] = sz;
+  if (sz == 0) return;
+  const uint64_t gb = d.beg + st;
+  if (sz <= C) {
+    sort_small<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, gb, sz, 0, a.kind, sm);
+    return;
+  }
+  if (a.next_segs) {
+    __shared__ uint32_t slot;
+    if (threadIdx.x == 0) {
+      slot = atomicAdd(&a.next_ctl->nsegs, 1u);
+      if (slot < a.next_cap) {
+        SegDesc nd = {};
+        nd.beg = gb;
+        nd.len = sz;
+        nd.p = 0;
+        nd.seed = derive_seed(d.seed, d.depth + 1, b);
+        nd.depth = d.depth + 1;
+        nd.parent_bkt = b;
+        a.next_segs[slot] = nd;
+      } else {
+        atomicOr(&a.gctl->status, ST_LIST_FULL);
+      }
+    }
+    __syncthreads();
+    if (slot < a.next_cap) return;
+  }
+  if (threadIdx.x == 0) atomicOr(&a.gctl->status, ST_FALLBACK);
+  KT* alt = (a.dst == a.out) ? (KT*)a.tmp : (KT*)a.dst;
+  void* valt = (a.dst == a.out) ? a.vtmp : a.vdst;
+  sort_big_wg<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, alt, valt, gb, sz, 0, a.kind, sm);
+}
+
+// ------------------------------------------------- entry kernels
+
+// Zero the control block and write the single top-level segment.
+__global__ void k_init_single(Ctl* g, SegDesc* segs, uint64_t n, uint32_t p, uint32_t m, uint32_t stride,
+                              uint64_t seed) {
+  if (threadIdx.x == 0) {
+    *g = Ctl{};
+    g->lv[0].nsegs = 1;
+    SegDesc d = {};
+    d.beg = 0;
+    d.len = (uint32_t)n;
+    d.p = p;
+    d.m = m;
+    d.stride = stride;
+    d.seed = seed;
+    segs[0] = d;
+  }
+}
+
+__global__ void k_init_ctl(Ctl* g) {
+  if (threadIdx.x == 0) *g = Ctl{};
+}
+
+// Segmented input: segments longer than C go to the top level's list, the
+// others to the small list (sorted directly by one work-group each).
+__global__ void k_seg_init(Ctl* g, const int64_t* off, uint32_t nseg, uint32_t C, SegDesc* top, uint32_t top_cap,
+                           SmallEnt* small, uint64_t seed) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
+    int64_t b = off[i], e = off[i + 1];
+    if (e < b) {
+      atomicOr(&g->status, ST_BAD_OFFSETS);
+      continue;
+    }
+    uint64_t len = (uint64_t)(e - b);
+    if (len == 0) continue;
+    if (len <= C) {
+      uint32_t s = atomicAdd(&g->nsmall, 1u);
+      small[s] = SmallEnt{(uint64_t)b, (uint32_t)len, 0};
+    } else {
+      uint32_t s = atomicAdd(&g->lv[0].nsegs, 1u);
+      if (s >= top_cap) { atomicOr(&g->status, ST_LIST_FULL); continue; }
+      SegDesc d = {};
+      d.beg = (uint64_t)b;
+      d.len = (uint32_t)len;
+      d.p = 0;
+      d.seed = derive_seed(seed, 0, i);
+      d.depth = 0;
+      top[s] = d;
+    }
+  }
+}
+
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_sort_small_list(Ctl* g, const SmallEnt* list, const void* src,
+                                                        const void* vsrc, void* out, void* vout, int kind,
+                                                        int iota) {
+  using KT = typename KeyOf<KW>::T;
+  __shared__ SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> sm;
+  if (blockIdx.x >= g->nsmall) return;
+  SmallEnt e = list[blockIdx.x];
+  // an iota payload is the index inside the segment (0-based from e.beg)
+  sort_small<KW, VW>((const KT*)src, iota ? nullptr : vsrc, (KT*)out, vout, e.beg, e.len, 0, kind, sm);
+}
+
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_sort_direct(const void* src, const void* vsrc, void* out, void* vout,
+                                                    uint64_t beg, uint32_t len, int kind) {
+  using KT = typename KeyOf<KW>::T;
+  __shared__ SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> sm;
+  sort_small<KW, VW>((const KT*)src, vsrc, (KT*)out, vout, beg, len, 0, kind, sm);
+}
+
+// One work-group sorts the whole array (used only when no p >= 2 meets the
+// preconditions and the array exceeds one work-group).
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_sort_whole(const void* src, const void* vsrc, void* out, void* vout,
+                                                   void* tmp, void* vtmp, uint64_t n, int kind) {
+  using KT = typename KeyOf<KW>::T;
+  __shared__ SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> sm;
+  sort_big_wg<KW, VW>((const KT*)src, vsrc, (KT*)out, vout, (KT*)tmp, vtmp, 0, n, 0, kind, sm);
+}
+
+// Block bounds of regular sampling: block k = [floor(k n/p), floor((k+1) n/p)).
+__global__ void k_block_offsets(int64_t* off, uint64_t n, uint32_t p) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= p; k += gridDim.x * blockDim.x)
+    off[k] = (int64_t)(((uint64_t)k * n) / p);
+}
+
+// Backward of a row-wise sort: grad_x[r, perm[r, j]] = grad_y[r, j].
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter_grad(const T* gy, const int64_t* perm, T* gx, uint64_t rows,
+                                                      uint64_t cols) {
+  const uint64_t total = rows * cols;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (uint64_t)gridDim.x * 256) {
+    uint64_t r = i / cols;
+    int64_t pj = perm[i];
+    if (pj >= 0 && (uint64_t)pj < cols) gx[r * cols + (uint64_t)pj] = gy[i];
+  }
+}
+
+}  // namespace ss
