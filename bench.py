@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--sampling", default="random", choices=["random", "regular"])
     ap.add_argument("--dist", default="uniform")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--flags", type=int, default=0, help="extra SS_F_* bits (tuning experiments)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-log2n", type=int, default=24, help="CPU baseline sample size (log2)")
     ap.add_argument("--profile", action="store_true", help="per-kernel table on stderr")
@@ -98,7 +99,7 @@ def bench_sort(args):
     keys = workloads.keys_2p26(n, args.dist, seed, np.int32)
     kd = torch.from_numpy(keys).to(dev)
     out = torch.empty_like(kd)
-    prm = api.params(p=args.p, s=args.s, sampling=args.sampling, seed=1234, tile=args.tile)
+    prm = api.params(p=args.p, s=args.s, sampling=args.sampling, seed=1234, tile=args.tile, flags=args.flags)
     info = api.stage_layout(n, native.SS_I32, native.SS_V_NONE, prm)
     ws = api._workspace(api.workspace_size(n, native.SS_I32, native.SS_V_NONE, prm), dev)
     for _ in range(args.warmup):
@@ -131,7 +132,7 @@ def bench_sort(args):
         "dtype": "i32", "data": "synthetic",
         "config": {"workload": f"sample sort of 2^{args.log2n} int32 keys ({args.dist}), keys only",
                    "n": n, "p": args.p, "p_eff": info.p_eff, "s": args.s, "sampling": args.sampling,
-                   "levels_below_top": info.levels, "dist": args.dist, "seed": seed},
+                   "levels_below_top": info.levels, "dist": args.dist, "seed": seed, "flags": args.flags},
         "hbm_frac_20B_per_key": round(gk * 20 / HBM_PEAK_GBS, 4),
         "roofline": roof,
         "kernels": kernel_table(rep, args.steps),

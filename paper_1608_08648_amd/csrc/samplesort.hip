@@ -42,11 +42,11 @@ int fail(int code, const char* fmt, ...) {
 // ---------------------------------------------------------------- profiling
 enum ProfKind {
   PK_INIT, PK_PLAN, PK_SAMPLE, PK_SAMPLE_SORT, PK_SAMPLE_MERGE, PK_TREE, PK_CLASSIFY, PK_SCAN, PK_SCATTER,
-  PK_BUCKET_SORT, PK_SMALL_SORT, PK_BLOCK_SORT_REGULAR, PK_GRAD, PK_COUNT
+  PK_BUCKET_SORT, PK_BUCKET_LEFT, PK_SMALL_SORT, PK_BLOCK_SORT_REGULAR, PK_GRAD, PK_COUNT
 };
 const char* const PROF_NAMES[PK_COUNT] = {
     "init", "plan", "sample", "sample_sort", "sample_merge", "tree", "classify", "scan", "scatter",
-    "bucket_sort", "small_sort", "regular_blocks", "scatter_grad"};
+    "bucket_sort", "bucket_leftover", "small_sort", "regular_blocks", "scatter_grad"};
 
 struct Prof {
   bool on = false;
@@ -107,6 +107,8 @@ uint32_t small_cap(int KW, int VW) {
   return (uint32_t)NT * (s <= 4 ? 64 : (s <= 8 ? 32 : 16));
 }
 uint32_t sample_cap(int KW) { return (uint32_t)NT * (KW == 4 ? 32 : 16); }
+// keys-only buckets up to this size are sorted by the slot sort
+uint32_t slot_cap(int KW) { return KW == 4 ? (uint32_t)SlotCap<4>::C : (uint32_t)SlotCap<8>::C; }
 uint32_t split_chunk(int KW, int VW) { return (uint32_t)NT * ((KW + VW <= 4) ? 8 : 4); }
 
 constexpr size_t ALIGN = 256;
@@ -142,15 +144,18 @@ uint32_t p_effective(uint64_t n, uint32_t p, uint32_t s, int mode) {
   return 1;
 }
 
-uint32_t default_tile(uint32_t p, uint32_t chunk) {
+// Tiles are whole multiples of 8192 keys (the split chunk and id block of
+// every key width).
+constexpr uint32_t TILE_UNIT = 8192;
+uint32_t default_tile(uint32_t p) {
   uint64_t t = std::max<uint64_t>(16384, 16ull * p);
-  return (uint32_t)(cdiv(t, chunk) * chunk);
+  return (uint32_t)(cdiv(t, TILE_UNIT) * TILE_UNIT);
 }
 
 struct LevelPlan {
   uint32_t tile = 0, seg_cap = 0, pmax = 256, p_cap = 256, target = 0, s = 1;
   uint64_t samp_cap = 0, tiles_cap = 0, hist_cap = 0, bkt_cap = 0;
-  size_t o_segs = 0, o_sord = 0, o_stag = 0, o_tree = 0, o_ttag = 0, o_hist = 0, o_part = 0;
+  size_t o_segs = 0, o_sord = 0, o_stag = 0, o_tree = 0, o_ttag = 0, o_hist = 0, o_part = 0, o_left = 0;
 };
 
 struct LevelsPlan {
@@ -169,9 +174,11 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
                  LevelsPlan* P) {
   const uint32_t C = small_cap(ty.KW, ty.VW);
   const uint32_t Cs = sample_cap(ty.KW);
-  const uint32_t CH = split_chunk(ty.KW, ty.VW);
   const double f = spread(s);
-  const uint32_t target = (uint32_t)std::max(1024.0, (double)C / (1.2 * f));
+  // automatically sized buckets aim at about half of what the bucket sort
+  // takes in one work-group (the slot sort for keys only)
+  const uint32_t target = ty.VW == 0 ? (uint32_t)(0.53 * slot_cap(ty.KW))
+                                     : (uint32_t)std::max(1024.0, (double)C / (1.2 * f));
   P->nlev = 0;
   uint64_t est = 0;
   for (int l = 0; l < MAX_LEVELS; l++) {
@@ -181,7 +188,7 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
     if (l == 0 && p0) {
       lv.p_cap = p0;
       lv.pmax = p0 > 256 ? 4096 : 256;
-      lv.tile = tile_req ? (uint32_t)(cdiv(tile_req, CH) * CH) : default_tile(p0, CH);
+      lv.tile = tile_req ? (uint32_t)(cdiv(tile_req, TILE_UNIT) * TILE_UNIT) : default_tile(p0);
       lv.seg_cap = 1;
       lv.samp_cap = m0;
       lv.tiles_cap = cdiv(N, lv.tile);
@@ -191,7 +198,7 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
     } else {
       lv.p_cap = p_cap;
       lv.pmax = p_cap > 256 ? 4096 : 256;
-      lv.tile = tile_req ? (uint32_t)(cdiv(tile_req, CH) * CH) : default_tile(p_cap, CH);
+      lv.tile = tile_req ? (uint32_t)(cdiv(tile_req, TILE_UNIT) * TILE_UNIT) : default_tile(p_cap);
       uint64_t sc = (l == 0) ? seg_cap0 : std::min<uint64_t>(P->lv[l - 1].bkt_cap, N / (C + 1) + 1);
       sc = std::min<uint64_t>(sc, N / (C + 1) + 1);
       lv.seg_cap = (uint32_t)std::max<uint64_t>(sc, 1);
@@ -209,6 +216,7 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
     lv.o_ttag = (ty.KW == 8) ? L.take(4 * std::max<uint64_t>(lv.bkt_cap, 1)) : 0;
     lv.o_hist = L.take(4 * std::max<uint64_t>(lv.hist_cap, 1));
     lv.o_part = L.take(4 * (cdiv(std::max<uint64_t>(lv.hist_cap, 1), SCAN_BLOCK) + 1));
+    lv.o_left = L.take(sizeof(SmallEnt) * std::max<uint64_t>(lv.bkt_cap, 1));
     if (l == 0 && p0 && m0 > Cs) {
       P->big_sample = true;
       P->merge_passes = 0;
@@ -219,6 +227,15 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
     P->nlev = l + 1;
     if (!recurse || est <= C) break;
   }
+}
+
+// Bytes of the bucket-index buffer: a tile-sized slice per tile of the
+// level with the most tiles, 2 bytes per key (1 when p <= 256).
+uint64_t ids_bytes(const LevelsPlan& lp) {
+  uint64_t b = 0;
+  for (int l = 0; l < lp.nlev; l++)
+    b = std::max<uint64_t>(b, lp.lv[l].tiles_cap * lp.lv[l].tile * (lp.lv[l].pmax > 256 ? 2 : 1));
+  return b;
 }
 
 // Full plan of one call.
@@ -234,7 +251,7 @@ struct Plan {
   uint64_t m = 0;
   bool regular = false;
   LevelsPlan lp;
-  size_t o_ctl = 0, o_tmp = 0, o_vtmp = 0;
+  size_t o_ctl = 0, o_tmp = 0, o_vtmp = 0, o_ids = 0;
   size_t o_exp_so = 0, o_exp_st = 0, o_exp_po = 0, o_exp_pt = 0, o_exp_cnt = 0;
   bool exp = false;
   size_t o_small = 0;      // segmented: small-segment list
@@ -311,6 +328,7 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   P->o_vtmp = ty.VW ? L.take((size_t)ty.VW * n) : 0;
   const bool recurse = !(prm.flags & SS_F_NO_RECURSION);
   plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp);
+  if (ty.VW == 0 && !(prm.flags & SS_F_RECLASSIFY)) P->o_ids = L.take(ids_bytes(P->lp));
   if (P->regular) {
     // blocks sorted with their in-block index as payload (Alg. 1 step 1)
     P->o_regk = L.take((size_t)ty.KW * n);
@@ -355,6 +373,7 @@ int plan_segmented(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, cons
     uint64_t seg_cap0 = std::min<uint64_t>(nseg, total / (C + 1) + 1);
     const bool recurse = !(prm.flags & SS_F_NO_RECURSION);
     plan_levels(L, ty, total, seg_cap0, maxlen, 0, 0, 0, prm.s, p_cap, prm.tile, recurse, &P->lp);
+    if (ty.VW == 0 && !(prm.flags & SS_F_RECLASSIFY)) P->o_ids = L.take(ids_bytes(P->lp));
   }
   P->bytes = L.cur;
   return SS_OK;
@@ -420,6 +439,9 @@ LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void*
   a.tree_tag = lv.o_ttag ? (uint32_t*)(ws + lv.o_ttag) : nullptr;
   a.hist = (uint32_t*)(ws + lv.o_hist);
   a.scan_part = (uint32_t*)(ws + lv.o_part);
+  a.left = (SmallEnt*)(ws + lv.o_left);
+  a.ids = P.o_ids ? (void*)(ws + P.o_ids) : nullptr;
+  a.nleft = &g->nleft[l];
   if (P.exp && l == 0) {
     a.exp_smp_ord = (uint64_t*)(ws + P.o_exp_so);
     a.exp_smp_tag = (uint64_t*)(ws + P.o_exp_st);
@@ -431,7 +453,8 @@ LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void*
   a.s = lv.s;
   a.p_cap = lv.p_cap;
   a.target = lv.target;
-  a.kind = P.ty.kind;
+  a.kin = (l == 0) ? P.ty.kind : 0;   // the top level writes unsigned images for every deeper pass
+  a.kout = P.ty.kind;
   a.iota = (l == 0 && P.ty.iota) ? 1 : 0;
   return a;
 }
@@ -490,10 +513,20 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
     LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, a);
     LAUNCH(PK_SCAN, k_scan_down, dim3(nb), dim3(NT), 0, st, a);
     LAUNCH_CHECK();
-    if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
-    else LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 256>), dim3(tiles), dim3(NT), 0, st, a);
-    LAUNCH_CHECK();
-    LAUNCH(PK_BUCKET_SORT, (k_bucket_sort<KW, VW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a, exp);
+    if constexpr (VW == 0) {
+      // keys only: equal keys are bit-identical, so placement order inside a bucket is free
+      if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter_keys<KW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
+      else LAUNCH(PK_SCATTER, (k_scatter_keys<KW, 256>), dim3(tiles), dim3(NT), 0, st, a);
+      LAUNCH_CHECK();
+      LAUNCH(PK_BUCKET_SORT, (k_bucket_sort_keys<KW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a, exp);
+      LAUNCH_CHECK();
+      LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<KW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a);
+    } else {
+      if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
+      else LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 256>), dim3(tiles), dim3(NT), 0, st, a);
+      LAUNCH_CHECK();
+      LAUNCH(PK_BUCKET_SORT, (k_bucket_sort<KW, VW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a, exp);
+    }
     LAUNCH_CHECK();
   }
   return SS_OK;

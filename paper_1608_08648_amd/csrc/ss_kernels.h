@@ -89,6 +89,7 @@ struct Ctl {              // device control block at the start of the workspace
   uint32_t nsmall;        // entries in the small-segment list
   uint32_t pad[2];
   LevelCtl lv[MAX_LEVELS];
+  uint32_t nleft[MAX_LEVELS];   // buckets the slot sort handed on, per level
 };
 
 enum : uint32_t {
@@ -127,11 +128,16 @@ struct LevelArgs {
   uint64_t* exp_spl_ord;
   uint64_t* exp_spl_tag;
   uint64_t* exp_counts;
+  void* ids;               // bucket of every key, written by k_classify for k_scatter_keys (or null)
+  SmallEnt* left;          // buckets handed from the slot sort to the radix sort (keys only)
+  uint32_t* nleft;
   uint32_t tile;           // keys per tile in the split passes
   uint32_t s;              // oversampling factor for automatically sized segments
   uint32_t p_cap;          // largest p for automatically sized segments
   uint32_t target;         // aimed-at bucket size for automatically sized segments
-  int kind;                // 0 unsigned, 1 signed, 2 float
+  int kin;                 // key map of src: 0 unsigned, 1 signed, 2 float (the top level reads the
+                           // caller's keys; every deeper buffer holds the unsigned images, kin = 0)
+  int kout;                // key map of the final output (the caller's key type)
   int iota;                // 1: payload = index in segment, generated (top level)
 };
 
@@ -161,6 +167,15 @@ __device__ __forceinline__ uint64_t derive_seed(uint64_t seed, uint32_t depth, u
   return sm64_mix(seed ^ sm64_mix(((uint64_t)depth << 32) + bucket));
 }
 
+// stored bucket index of a key: one byte when p <= 256
+template <int PMAX> struct BucketId { using T = typename std::conditional<(PMAX <= 256), uint8_t, uint16_t>::type; };
+// Keys move through classify and the keys-only split in blocks of
+// IdBlock::U * NT keys: thread t takes keys i0 + u*NT + t (coalesced), and
+// stores their U bucket indices contiguously at ids[tile base + i0 + t*U + u]
+// (one wide store / load per thread).  Tiles are multiples of the block.
+template <typename T, int U> struct alignas(sizeof(T) * U) IdVec { T x[U]; };
+template <int KW> struct IdBlock { static constexpr int U = KW == 4 ? 16 : 8; static constexpr int B = U * NT; };
+
 // search tree in LDS: 4-byte keys as packed u64, 8-byte keys as (ord, tag)
 template <int KW, int PMAX>
 struct TreeLds;
@@ -177,6 +192,20 @@ struct TreeLds<4, PMAX> {
     uint32_t k = 1;
     for (uint32_t l = 0; l < lgp; l++) k = 2 * k + (node[k] < e ? 1u : 0u);
     return k - p;
+  }
+  // U independent walks advanced level by level, so their LDS reads overlap
+  template <int U>
+  __device__ __forceinline__ void classify_many(const uint32_t (&ord)[U], const uint32_t (&tag)[U], uint32_t lgp,
+                                                uint32_t p, uint32_t (&b)[U]) const {
+    uint64_t e[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) { e[u] = ((uint64_t)ord[u] << 32) | tag[u]; b[u] = 1; }
+    for (uint32_t l = 0; l < lgp; l++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) b[u] = 2 * b[u] + (node[b[u]] < e[u] ? 1u : 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) b[u] -= p;
   }
 };
 template <int PMAX>
@@ -195,6 +224,22 @@ struct TreeLds<8, PMAX> {
       k = 2 * k + (less ? 1u : 0u);
     }
     return k - p;
+  }
+  template <int U>
+  __device__ __forceinline__ void classify_many(const uint64_t (&ord)[U], const uint32_t (&tg)[U], uint32_t lgp,
+                                                uint32_t p, uint32_t (&b)[U]) const {
+#pragma unroll
+    for (int u = 0; u < U; u++) b[u] = 1;
+    for (uint32_t l = 0; l < lgp; l++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        uint64_t a = node[b[u]];
+        bool less = (a < ord[u]) || (a == ord[u] && tag[b[u]] < tg[u]);
+        b[u] = 2 * b[u] + (less ? 1u : 0u);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) b[u] -= p;
   }
 };
 
@@ -218,7 +263,7 @@ struct SmallLds {
 template <int KW, int VW, int K, int KMAX>
 __device__ __forceinline__ void sort_small_k(const typename KeyOf<KW>::T* src, const void* vsrc,
                              typename KeyOf<KW>::T* out, void* vout, uint64_t beg, uint32_t len,
-                             uint64_t iota_base, int kind, SmallLds<KW, VW, KMAX>& sm) {
+                             uint64_t iota_base, int kin, int kout, SmallLds<KW, VW, KMAX>& sm) {
   using KT = typename KeyOf<KW>::T;
   using VT = typename ValOf<VW>::T;
   constexpr bool HASV = VW != 0;
@@ -231,7 +276,7 @@ __device__ __forceinline__ void sort_small_k(const typename KeyOf<KW>::T* src, c
     int i = r * NT + t;
     int j = pad_idx<K>(i);
     if (i < (int)len) {
-      sm.xh[j] = to_ord(src[beg + i], kind);
+      sm.xh[j] = to_ord(src[beg + i], kin);
       if constexpr (HASV) {
         if (vsrc) xv[j] = ((const VT*)vsrc)[beg + i];
         else xv[j] = (VT)(iota_base + i);
@@ -257,7 +302,7 @@ __device__ __forceinline__ void sort_small_k(const typename KeyOf<KW>::T* src, c
     int i = r * NT + t;
     if (i < (int)len) {
       int j = pad_idx<K>(i);
-      out[beg + i] = from_ord(sm.xh[j], kind);
+      out[beg + i] = from_ord(sm.xh[j], kout);
       if constexpr (HASV) ((VT*)vout)[beg + i] = xv[j];
     }
   }
@@ -266,13 +311,16 @@ __device__ __forceinline__ void sort_small_k(const typename KeyOf<KW>::T* src, c
 
 template <int KW, int VW>
 __device__ __forceinline__ void sort_small(const typename KeyOf<KW>::T* src, const void* vsrc, typename KeyOf<KW>::T* out,
-                           void* vout, uint64_t beg, uint32_t len, uint64_t iota_base, int kind,
+                           void* vout, uint64_t beg, uint32_t len, uint64_t iota_base, int kin, int kout,
                            SmallLds<KW, VW, SmallCap<KW, VW>::KMAX>& sm) {
   constexpr int KMAX = SmallCap<KW, VW>::KMAX;
-  if (len <= (uint32_t)NT * 1) sort_small_k<KW, VW, 1, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kind, sm);
-  else if (len <= (uint32_t)NT * 4) sort_small_k<KW, VW, 4, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kind, sm);
-  else if (len <= (uint32_t)NT * 16) sort_small_k<KW, VW, 16, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kind, sm);
-  else sort_small_k<KW, VW, KMAX, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kind, sm);
+  if (len <= (uint32_t)NT * 1) sort_small_k<KW, VW, 1, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kin, kout, sm);
+  else if (len <= (uint32_t)NT * 4) sort_small_k<KW, VW, 4, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kin, kout, sm);
+  else if (len <= (uint32_t)NT * 8) sort_small_k<KW, VW, 8, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kin, kout, sm);
+  else if (len <= (uint32_t)NT * 16) sort_small_k<KW, VW, 16, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kin, kout, sm);
+  else if (KMAX > 32 && len <= (uint32_t)NT * 32)
+    sort_small_k<KW, VW, (KMAX > 32 ? 32 : KMAX), KMAX>(src, vsrc, out, vout, beg, len, iota_base, kin, kout, sm);
+  else sort_small_k<KW, VW, KMAX, KMAX>(src, vsrc, out, vout, beg, len, iota_base, kin, kout, sm);
 }
 
 // One work-group sorts a segment of any length: LDS-sorted chunks of C
@@ -282,7 +330,7 @@ __device__ __forceinline__ void sort_small(const typename KeyOf<KW>::T* src, con
 template <int KW, int VW>
 __device__ void sort_big_wg(const typename KeyOf<KW>::T* cur, const void* vcur, typename KeyOf<KW>::T* out,
                             void* vout, typename KeyOf<KW>::T* alt, void* valt, uint64_t beg, uint64_t len,
-                            uint64_t iota_base, int kind, SmallLds<KW, VW, SmallCap<KW, VW>::KMAX>& sm) {
+                            uint64_t iota_base, int kin, int kout, SmallLds<KW, VW, SmallCap<KW, VW>::KMAX>& sm) {
   using KT = typename KeyOf<KW>::T;
   using VT = typename ValOf<VW>::T;
   constexpr bool HASV = VW != 0;
@@ -298,7 +346,7 @@ __device__ void sort_big_wg(const typename KeyOf<KW>::T* cur, const void* vcur, 
   for (uint64_t c = 0; c < nch; c++) {
     uint64_t cb = c * C;
     uint32_t cl = (uint32_t)((len - cb) < C ? (len - cb) : C);
-    sort_small<KW, VW>(cur, vcur, b0, vb0, beg + cb, cl, iota_base + cb, kind, sm);
+    sort_small<KW, VW>(cur, vcur, b0, vb0, beg + cb, cl, iota_base + cb, kin, kout, sm);
   }
   if (passes == 0) return;
   __threadfence_block();
@@ -318,15 +366,15 @@ __device__ void sort_big_wg(const typename KeyOf<KW>::T* cur, const void* vcur, 
       for (uint64_t d0 = 0; d0 < tot; d0 += (uint64_t)NT * MERGE_V) {
         uint64_t d = d0 + (uint64_t)threadIdx.x * MERGE_V;
         if (d < tot) {
-          auto ga = [&](uint64_t i) { return to_ord(A[i], kind); };
-          auto gb = [&](uint64_t i) { return to_ord(B[i], kind); };
+          auto ga = [&](uint64_t i) { return to_ord(A[i], kout); };
+          auto gb = [&](uint64_t i) { return to_ord(B[i], kout); };
           uint64_t i = merge_path(d, la, lb, ga, gb, [](KT x, KT y) { return x <= y; });
           uint64_t j = d - i;
           for (int v = 0; v < MERGE_V && d + v < tot; v++) {
             bool takeA;
             if (i >= la) takeA = false;
             else if (j >= lb) takeA = true;
-            else takeA = to_ord(A[i], kind) <= to_ord(B[j], kind);
+            else takeA = to_ord(A[i], kout) <= to_ord(B[j], kout);
             uint64_t dst = beg + pb + d + v;
             if (takeA) {
               o[dst] = A[i];
@@ -435,7 +483,7 @@ __global__ void __launch_bounds__(256) k_sample_random(LevelArgs a) {
     SegDesc d = a.segs[si];
     uint32_t j = g - d.samp_off;
     uint64_t pos = scale_to(sm64_at(d.seed, j), d.len);
-    KT key = to_ord(((const KT*)a.src)[d.beg + pos], a.kind);
+    KT key = to_ord(((const KT*)a.src)[d.beg + pos], a.kin);
     ((KT*)a.s_ord)[g] = key;
     a.s_tag[g] = (uint32_t)pos;
   }
@@ -639,7 +687,7 @@ __global__ void __launch_bounds__(256) k_sample_regular(LevelArgs a, const void*
     uint64_t rank = (j + 1) * x;
     if (rank > mk) rank = mk;
     uint64_t at = b + rank - 1;
-    ((KT*)a.s_ord)[g] = to_ord(((const KT*)skeys)[at], a.kind);
+    ((KT*)a.s_ord)[g] = to_ord(((const KT*)skeys)[at], a.kin);
     a.s_tag[g] = (uint32_t)(b + sidx[at]);
   }
 }
@@ -649,6 +697,7 @@ __global__ void __launch_bounds__(256) k_sample_regular(LevelArgs a, const void*
 template <int KW, int PMAX>
 __global__ void __launch_bounds__(NT) k_classify(LevelArgs a) {
   using KT = typename KeyOf<KW>::T;
+  using IdT = typename BucketId<PMAX>::T;
   __shared__ TreeLds<KW, PMAX> tr;
   __shared__ uint32_t cnt[PMAX];
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -664,15 +713,35 @@ __global__ void __launch_bounds__(NT) k_classify(LevelArgs a) {
   const uint32_t t1 = min(t0 + a.tile, d.len);
   const KT* src = (const KT*)a.src + d.beg;
   uint32_t cur = ~0u, run = 0;
-  for (uint32_t i = t0 + threadIdx.x; i < t1; i += NT) {
-    KT key = to_ord(src[i], a.kind);
-    uint32_t b = tr.classify(key, i, d.lgp, d.p);
-    if (b != cur) {
-      if (run) atomicAdd(&cnt[cur], run);
-      cur = b;
-      run = 0;
+  constexpr int U = IdBlock<KW>::U;   // keys per thread in flight
+  IdT* tile_ids = a.ids ? (IdT*)a.ids + (uint64_t)tile * a.tile : nullptr;
+  for (uint32_t i0 = t0; i0 < t1; i0 += U * NT) {
+    KT key[U];
+    uint32_t tag[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      uint32_t i = i0 + u * NT + threadIdx.x;
+      tag[u] = i;
+      key[u] = i < t1 ? to_ord(src[i], a.kin) : KT(0);
     }
-    run++;
+    tr.template classify_many<U>(key, tag, d.lgp, d.p, b);
+    if (tile_ids) {
+      IdVec<IdT, U> v;
+#pragma unroll
+      for (int u = 0; u < U; u++) v.x[u] = (IdT)b[u];
+      *(IdVec<IdT, U>*)(tile_ids + (i0 - t0) + threadIdx.x * U) = v;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (i0 + u * NT + threadIdx.x < t1) {
+        if (b[u] != cur) {
+          if (run) atomicAdd(&cnt[cur], run);
+          cur = b[u];
+          run = 0;
+        }
+        run++;
+      }
+    }
   }
   if (run) atomicAdd(&cnt[cur], run);
   __syncthreads();
@@ -787,7 +856,7 @@ __global__ void __launch_bounds__(NT) k_scatter(LevelArgs a) {
       int i = r * NT + t;
       if (i < cn) {
         int j = pad_idx<KS>(i);
-        sm.ck[j] = src[c0 + i];
+        sm.ck[j] = to_ord(src[c0 + i], a.kin);
         if constexpr (HASV) {
           if (a.iota) cv[j] = (VT)(c0 + i);
           else cv[j] = vsrc[d.beg + c0 + i];
@@ -799,15 +868,20 @@ __global__ void __launch_bounds__(NT) k_scatter(LevelArgs a) {
     uint32_t w[KS];
     uint32_t lo[KS];
     NoVal nv[KS];
+    {
+      KT key[KS];
+      uint32_t tag[KS], bk[KS];
 #pragma unroll
-    for (int k = 0; k < KS; k++) {
-      int i = t * KS + k;
-      if (i < cn) {
-        KT key = to_ord(sm.ck[pad_idx<KS>(i)], a.kind);
-        uint32_t b = sm.tr.classify(key, c0 + i, d.lgp, d.p);
-        w[k] = (b << 16) | (uint32_t)i;
-      } else {
-        w[k] = ~0u;
+      for (int k = 0; k < KS; k++) {
+        int i = t * KS + k;
+        key[k] = sm.ck[pad_idx<KS>(i)];   // slots past cn hold stale keys: ignored below
+        tag[k] = c0 + i;
+      }
+      sm.tr.template classify_many<KS>(key, tag, d.lgp, d.p, bk);
+#pragma unroll
+      for (int k = 0; k < KS; k++) {
+        int i = t * KS + k;
+        w[k] = (i < cn) ? ((bk[k] << 16) | (uint32_t)i) : ~0u;
       }
     }
     block_radix_sort<NT, KS, uint32_t, false, NoVal>(w, lo, nv, cn, sm.cnt, sm.xw, nullptr, nullptr, sm.red, 16);
@@ -831,30 +905,12 @@ __global__ void __launch_bounds__(NT) k_scatter(LevelArgs a) {
   }
 }
 
-// Buckets of the level: sort in LDS, or hand to the next level / fallback.
-template <int KW, int VW>
-__global__ void __launch_bounds__(NT) k_bucket_sort(LevelArgs a, int export_stages) {
+// Hand a bucket too large for one work-group to the next level's list, or
+// sort it with the one-work-group merge sort when no level is left.
+template <int KW, int VW, typename SM>
+__device__ __forceinline__ void bucket_overflow(const LevelArgs& a, const SegDesc& d, uint32_t b, uint64_t gb,
+                                                uint32_t sz, SM& sm) {
   using KT = typename KeyOf<KW>::T;
-  constexpr int KMAX = SmallCap<KW, VW>::KMAX;
-  constexpr uint32_t C = SmallCap<KW, VW>::C;
-  __shared__ SmallLds<KW, VW, KMAX> sm;
-  const LevelCtl c = *a.ctl;
-  const uint32_t x = blockIdx.x;
-  if (x >= c.total_buckets) return;
-  const uint32_t si = find_seg(a.segs, c.nsegs, x, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
-  const SegDesc d = a.segs[si];
-  const uint32_t b = x - d.bkt_off;
-  const uint32_t base = a.hist[d.hist_off];
-  const uint32_t st = a.hist[d.hist_off + (uint64_t)b * d.ntiles] - base;
-  const uint32_t en = (b + 1 < d.p) ? a.hist[d.hist_off + (uint64_t)(b + 1) * d.ntiles] - base : d.len;
-  const uint32_t sz = en - st;
-  if (export_stages && d.depth == 0 && si == 0 && threadIdx.x == 0) a.exp_counts[b] = sz;
-  if (sz == 0) return;
-  const uint64_t gb = d.beg + st;
-  if (sz <= C) {
-    sort_small<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, gb, sz, 0, a.kind, sm);
-    return;
-  }
   if (a.next_segs) {
     __shared__ uint32_t slot;
     if (threadIdx.x == 0) {
@@ -878,7 +934,352 @@ __global__ void __launch_bounds__(NT) k_bucket_sort(LevelArgs a, int export_stag
   if (threadIdx.x == 0) atomicOr(&a.gctl->status, ST_FALLBACK);
   KT* alt = (a.dst == a.out) ? (KT*)a.tmp : (KT*)a.dst;
   void* valt = (a.dst == a.out) ? a.vtmp : a.vdst;
-  sort_big_wg<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, alt, valt, gb, sz, 0, a.kind, sm);
+  sort_big_wg<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, alt, valt, gb, sz, 0, 0, a.kout, sm);
+}
+
+// Buckets of the level: sort in LDS, or hand to the next level / fallback.
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_bucket_sort(LevelArgs a, int export_stages) {
+  using KT = typename KeyOf<KW>::T;
+  constexpr int KMAX = SmallCap<KW, VW>::KMAX;
+  constexpr uint32_t C = SmallCap<KW, VW>::C;
+  __shared__ SmallLds<KW, VW, KMAX> sm;
+  const LevelCtl c = *a.ctl;
+  const uint32_t x = blockIdx.x;
+  if (x >= c.total_buckets) return;
+  const uint32_t si = find_seg(a.segs, c.nsegs, x, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
+  const SegDesc d = a.segs[si];
+  const uint32_t b = x - d.bkt_off;
+  const uint32_t base = a.hist[d.hist_off];
+  const uint32_t st = a.hist[d.hist_off + (uint64_t)b * d.ntiles] - base;
+  const uint32_t en = (b + 1 < d.p) ? a.hist[d.hist_off + (uint64_t)(b + 1) * d.ntiles] - base : d.len;
+  const uint32_t sz = en - st;
+  if (export_stages && d.depth == 0 && si == 0 && threadIdx.x == 0) a.exp_counts[b] = sz;
+  if (sz == 0) return;
+  const uint64_t gb = d.beg + st;
+  if (sz <= C) {
+    sort_small<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, gb, sz, 0, 0, a.kout, sm);
+    return;
+  }
+  bucket_overflow<KW, VW>(a, d, b, gb, sz, sm);
+}
+
+// ------------------------------------------- keys-only (unstable) paths
+//
+// With no payload, keys that compare equal have identical bits, so the
+// output does not depend on the order equal keys take inside a bucket; only
+// bucket membership has to be exact (it is: classification still compares
+// key then position).  These kernels therefore place keys with LDS atomics
+// instead of a stable ranking.
+
+// Split: every key goes to its bucket's region for this tile.  Each chunk
+// is grouped by bucket in LDS (slots reserved with LDS atomics), then every
+// bucket's run is written out contiguously.
+template <int KW, int PMAX>
+struct ScatterKeysLds {
+  using KT = typename KeyOf<KW>::T;
+  static constexpr int CH = IdBlock<KW>::B;   // keys per chunk
+  TreeLds<KW, PMAX> tr;    // used only when no stored bucket indices are given
+  uint32_t gofs[PMAX];     // next free in-segment position of each bucket
+  uint32_t ccnt[PMAX];     // chunk count, then running slot of each bucket
+  uint32_t cst[PMAX];      // chunk start of each bucket
+  KT sk[CH];               // chunk keys grouped by bucket
+  uint16_t sb[CH];         // their buckets
+  alignas(8) uint32_t red[32];
+};
+
+template <int KW, int PMAX>
+__global__ void __launch_bounds__(NT) k_scatter_keys(LevelArgs a) {
+  using KT = typename KeyOf<KW>::T;
+  using IdT = typename BucketId<PMAX>::T;
+  using L = ScatterKeysLds<KW, PMAX>;
+  constexpr int CH = L::CH;
+  constexpr int U = CH / NT;
+  __shared__ L sm;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const LevelCtl c = *a.ctl;
+  if (tile >= c.total_tiles) return;
+  const uint32_t si = find_seg(a.segs, c.nsegs, tile, [](const SegDesc& d) { return (uint64_t)d.tile_off; });
+  const SegDesc d = a.segs[si];
+  const uint32_t tw = tile - d.tile_off;
+  const int t = threadIdx.x;
+  if (!a.ids) sm.tr.load(a.tree, a.tree_tag, d.tree_off, d.p);
+  const uint32_t base = a.hist[d.hist_off];
+  for (uint32_t b = t; b < d.p; b += NT) {
+    sm.gofs[b] = a.hist[d.hist_off + (uint64_t)b * d.ntiles + tw] - base;
+    sm.ccnt[b] = 0;
+  }
+  __syncthreads();
+  const uint32_t t0 = tw * a.tile;
+  const uint32_t t1 = min(t0 + a.tile, d.len);
+  const KT* src = (const KT*)a.src + d.beg;
+  const IdT* tile_ids = a.ids ? (const IdT*)a.ids + (uint64_t)tile * a.tile : nullptr;   // from k_classify
+  KT* dst = (KT*)a.dst + d.beg;
+  for (uint32_t c0 = t0; c0 < t1; c0 += CH) {
+    const uint32_t cn = min((uint32_t)CH, t1 - c0);
+    KT key[U];
+    uint32_t b[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      uint32_t i = u * NT + t;
+      key[u] = i < cn ? to_ord(src[c0 + i], a.kin) : KT(0);
+    }
+    if (tile_ids) {
+      IdVec<IdT, U> v = *(const IdVec<IdT, U>*)(tile_ids + (c0 - t0) + t * U);
+#pragma unroll
+      for (int u = 0; u < U; u++) b[u] = v.x[u];
+    } else {
+      uint32_t tag[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) tag[u] = c0 + u * NT + t;
+      sm.tr.template classify_many<U>(key, tag, d.lgp, d.p, b);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if ((uint32_t)(u * NT + t) < cn) atomicAdd(&sm.ccnt[b[u]], 1u);
+    __syncthreads();
+    // chunk starts (exclusive scan over the buckets); counters become cursors
+    {
+      constexpr int PER = (PMAX + NT - 1) / NT;
+      uint32_t v[PER], sum = 0;
+#pragma unroll
+      for (int j = 0; j < PER; j++) {
+        uint32_t bb = t * PER + j;
+        v[j] = bb < d.p ? sm.ccnt[bb] : 0u;
+        sum += v[j];
+      }
+      uint32_t tot;
+      uint32_t run = block_excl_scan<NT>(sum, sm.red, &tot);
+#pragma unroll
+      for (int j = 0; j < PER; j++) {
+        uint32_t bb = t * PER + j;
+        if (bb < d.p) { sm.cst[bb] = run; sm.ccnt[bb] = run; }
+        run += v[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if ((uint32_t)(u * NT + t) < cn) {
+        uint32_t pos = atomicAdd(&sm.ccnt[b[u]], 1u);
+        sm.sk[pos] = key[u];
+        sm.sb[pos] = (uint16_t)b[u];
+      }
+    }
+    __syncthreads();
+    // runs out, in order
+    for (uint32_t j = t; j < cn; j += NT) {
+      uint32_t bb = sm.sb[j];
+      dst[sm.gofs[bb] + (j - sm.cst[bb])] = sm.sk[j];
+    }
+    __syncthreads();
+    for (uint32_t bb = t; bb < d.p; bb += NT) {
+      sm.gofs[bb] += sm.ccnt[bb] - sm.cst[bb];
+      sm.ccnt[bb] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// Bucket sort of one bucket by counting into S value slots: slot(key) =
+// (key - min) >> sh is monotone in the key, so ordering the slots and then
+// each slot's few keys orders the bucket.  The bucket is read three times
+// (min/max, count, place); the re-reads hit L2.  Slot counts are 16-bit,
+// two per word.  Returns false (having written nothing) when a slot is too
+// crowded; the caller then radix-sorts.
+// LDS of the slot sort stays under 80 KB so two work-groups share a CU.
+template <int KW> struct SlotCap { static constexpr int C = KW == 4 ? 16128 : 8064; };
+constexpr int SLOT_LOG2 = 13;                   // S = 8192 slots
+constexpr uint32_t SLOT_MAX_FILL = 48;          // crowded-slot limit
+
+template <int KW>
+struct SlotLds {
+  using KT = typename KeyOf<KW>::T;
+  static constexpr int C = SlotCap<KW>::C;
+  KT placed[C];
+  uint32_t scnt[(1 << SLOT_LOG2) / 2];          // two 16-bit slot counters per word
+  alignas(8) uint64_t red[64];
+  uint32_t flag;
+};
+
+//
+// lo_known / hi_known: a bound on the bucket's keys is already known (from
+// its splitters: keys of bucket b lie between splitter b's key and splitter
+// b+1's key); otherwise it is found with one pass over the bucket.
+template <int KW>
+__device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, typename KeyOf<KW>::T* out, uint64_t beg,
+                                          uint32_t len, int kin, int kout, SlotLds<KW>& sm,
+                                          bool lo_known = false, typename KeyOf<KW>::T lo = 0, bool hi_known = false,
+                                          typename KeyOf<KW>::T hi = 0) {
+  using KT = typename KeyOf<KW>::T;
+  constexpr int S = 1 << SLOT_LOG2;
+  constexpr int W = S / 2;
+  const int t = threadIdx.x;
+  const KT* in = src + beg;
+  KT mn = ~KT(0), mx = 0;
+  if (!(lo_known && hi_known))
+  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NT) {
+    KT k[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      uint32_t i = i0 + u * NT + t;
+      k[u] = i < len ? to_ord(in[i], kin) : KT(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+      if (i0 + u * NT + t < len) { mn = k[u] < mn ? k[u] : mn; mx = k[u] > mx ? k[u] : mx; }
+  }
+  for (int q = t; q < W; q += NT) sm.scnt[q] = 0;
+  if (!(lo_known && hi_known)) block_minmax<NT>(mn, mx, (KT*)sm.red);   // (ends with a barrier)
+  else __syncthreads();
+  if (lo_known) mn = lo;
+  if (hi_known) mx = hi;
+  if (mn == mx) {                          // one key value: already sorted
+    for (uint32_t i = t; i < len; i += NT) out[beg + i] = from_ord(mn, kout);
+    return true;
+  }
+  const int bw = bit_width<KT>((KT)(mx - mn));
+  const int sh = bw > SLOT_LOG2 ? bw - SLOT_LOG2 : 0;
+  auto slot = [&](KT k) { return (uint32_t)((KT)(k - mn) >> sh); };
+  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NT) {
+    KT k[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      uint32_t i = i0 + u * NT + t;
+      k[u] = i < len ? to_ord(in[i], kin) : KT(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      if (i0 + u * NT + t < len) {
+        uint32_t q = slot(k[u]);
+        atomicAdd(&sm.scnt[q >> 1], 1u << (16 * (q & 1)));
+      }
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the slot counts (16-bit halves), and the fullest slot
+  {
+    constexpr int PER = W / NT;
+    uint32_t v[PER], sum = 0, mxc = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      v[j] = sm.scnt[t * PER + j];
+      uint32_t lo = v[j] & 0xFFFFu, hi = v[j] >> 16;
+      sum += lo + hi;
+      mxc = max(mxc, max(lo, hi));
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<NT>(sum, (uint32_t*)sm.red, &tot);
+    uint32_t wm = wave_max(mxc);
+    if (t == 0) sm.flag = 0;
+    __syncthreads();
+    if (lane_id() == 0 && wm > SLOT_MAX_FILL) atomicOr(&sm.flag, 1u);
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      uint32_t lo = v[j] & 0xFFFFu;
+      sm.scnt[t * PER + j] = run | ((run + lo) << 16);   // starts of slots 2w and 2w+1
+      run += lo + (v[j] >> 16);
+    }
+  }
+  __syncthreads();
+  // every thread reads the flag before any thread leaves (the caller reuses
+  // this LDS for the radix sort)
+  const bool crowded = sm.flag != 0;
+  __syncthreads();
+  if (crowded) return false;
+  // place: afterwards each slot's counter holds the slot's end
+  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NT) {
+    KT k[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      uint32_t i = i0 + u * NT + t;
+      k[u] = i < len ? to_ord(in[i], kin) : KT(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      if (i0 + u * NT + t < len) {
+        uint32_t q = slot(k[u]);
+        uint32_t sft = 16 * (q & 1);
+        uint32_t old = atomicAdd(&sm.scnt[q >> 1], 1u << sft);
+        sm.placed[(old >> sft) & 0xFFFFu] = k[u];
+      }
+    }
+  }
+  __syncthreads();
+  // order each slot: a key's rank = keys of its slot that are smaller, or
+  // equal and placed earlier
+  auto slot_end = [&](uint32_t q) { return (sm.scnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu; };
+  for (uint32_t i = t; i < len; i += NT) {
+    KT k = sm.placed[i];
+    uint32_t q = slot(k);
+    uint32_t s0 = q ? slot_end(q - 1) : 0u, s1 = slot_end(q);
+    uint32_t rank = 0;
+    for (uint32_t j = s0; j < s1; j++) {
+      KT o = sm.placed[j];
+      rank += (o < k || (o == k && j < i)) ? 1u : 0u;
+    }
+    out[beg + s0 + rank] = from_ord(k, kout);
+  }
+  __syncthreads();
+  return true;
+}
+
+// Keys only: slot-sort every bucket that fits; hand the others on.
+template <int KW>
+__global__ void __launch_bounds__(NT) k_bucket_sort_keys(LevelArgs a, int export_stages) {
+  using KT = typename KeyOf<KW>::T;
+  __shared__ SlotLds<KW> sm;
+  const LevelCtl c = *a.ctl;
+  const uint32_t x = blockIdx.x;
+  if (x >= c.total_buckets) return;
+  const uint32_t si = find_seg(a.segs, c.nsegs, x, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
+  const SegDesc d = a.segs[si];
+  const uint32_t b = x - d.bkt_off;
+  const uint32_t base = a.hist[d.hist_off];
+  const uint32_t st = a.hist[d.hist_off + (uint64_t)b * d.ntiles] - base;
+  const uint32_t en = (b + 1 < d.p) ? a.hist[d.hist_off + (uint64_t)(b + 1) * d.ntiles] - base : d.len;
+  const uint32_t sz = en - st;
+  if (export_stages && d.depth == 0 && si == 0 && threadIdx.x == 0) a.exp_counts[b] = sz;
+  if (sz == 0) return;
+  const uint64_t gb = d.beg + st;
+  // the bucket's key range from its splitters (ranks b and b+1), when both exist
+  auto spl_key = [&](uint32_t r) -> KT {          // key of splitter of rank r (1-based)
+    uint32_t z = __builtin_ctz(r);
+    uint32_t k = (1u << (d.lgp - 1 - z)) + (r >> (z + 1));
+    uint64_t node = ((const uint64_t*)a.tree)[d.tree_off + k];
+    if constexpr (KW == 4) return (KT)(node >> 32);
+    else return (KT)node;
+  };
+  const bool lo_k = b >= 1, hi_k = b + 1 < d.p;
+  const KT lo = lo_k ? spl_key(b) : KT(0);
+  const KT hi = hi_k ? spl_key(b + 1) : KT(0);
+  if (sz <= (uint32_t)SlotLds<KW>::C &&
+      slot_sort<KW>((const KT*)a.dst, (KT*)a.out, gb, sz, 0, a.kout, sm, lo_k, lo, hi_k, hi))
+    return;
+  if (threadIdx.x == 0) {
+    // (bucket index kept in pad: the next level derives its seed from it)
+    uint32_t k = atomicAdd(a.nleft, 1u);
+    a.left[k] = SmallEnt{gb, sz, x};
+  }
+}
+
+// Keys only: buckets the slot sort handed on -- radix sort in LDS, or the
+// next level / fallback when larger than one work-group.
+template <int KW>
+__global__ void __launch_bounds__(NT) k_bucket_leftover_keys(LevelArgs a) {
+  using KT = typename KeyOf<KW>::T;
+  constexpr uint32_t C = SmallCap<KW, 0>::C;
+  __shared__ SmallLds<KW, 0, SmallCap<KW, 0>::KMAX> sm;
+  if (blockIdx.x >= *a.nleft) return;
+  const SmallEnt e = a.left[blockIdx.x];
+  if (e.len <= C) {
+    sort_small<KW, 0>((const KT*)a.dst, nullptr, (KT*)a.out, nullptr, e.beg, e.len, 0, 0, a.kout, sm);
+    return;
+  }
+  const LevelCtl c = *a.ctl;
+  const uint32_t si = find_seg(a.segs, c.nsegs, e.pad, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
+  const SegDesc d = a.segs[si];
+  bucket_overflow<KW, 0>(a, d, e.pad - d.bkt_off, e.beg, e.len, sm);
 }
 
 // ------------------------------------------------- entry kernels
@@ -942,7 +1343,7 @@ __global__ void __launch_bounds__(NT) k_sort_small_list(Ctl* g, const SmallEnt* 
   if (blockIdx.x >= g->nsmall) return;
   SmallEnt e = list[blockIdx.x];
   // an iota payload is the index inside the segment (0-based from e.beg)
-  sort_small<KW, VW>((const KT*)src, iota ? nullptr : vsrc, (KT*)out, vout, e.beg, e.len, 0, kind, sm);
+  sort_small<KW, VW>((const KT*)src, iota ? nullptr : vsrc, (KT*)out, vout, e.beg, e.len, 0, kind, kind, sm);
 }
 
 template <int KW, int VW>
@@ -950,7 +1351,7 @@ __global__ void __launch_bounds__(NT) k_sort_direct(const void* src, const void*
                                                     uint64_t beg, uint32_t len, int kind) {
   using KT = typename KeyOf<KW>::T;
   __shared__ SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> sm;
-  sort_small<KW, VW>((const KT*)src, vsrc, (KT*)out, vout, beg, len, 0, kind, sm);
+  sort_small<KW, VW>((const KT*)src, vsrc, (KT*)out, vout, beg, len, 0, kind, kind, sm);
 }
 
 // One work-group sorts the whole array (used only when no p >= 2 meets the
@@ -960,7 +1361,7 @@ __global__ void __launch_bounds__(NT) k_sort_whole(const void* src, const void* 
                                                    void* tmp, void* vtmp, uint64_t n, int kind) {
   using KT = typename KeyOf<KW>::T;
   __shared__ SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> sm;
-  sort_big_wg<KW, VW>((const KT*)src, vsrc, (KT*)out, vout, (KT*)tmp, vtmp, 0, n, 0, kind, sm);
+  sort_big_wg<KW, VW>((const KT*)src, vsrc, (KT*)out, vout, (KT*)tmp, vtmp, 0, n, 0, kind, kind, sm);
 }
 
 // Block bounds of regular sampling: block k = [floor(k n/p), floor((k+1) n/p)).
