@@ -104,15 +104,21 @@ def segmented_keys(count, seed, dtype=np.int32, max_log2=20):
 
 
 def tie_free_rows(rows, cols, seed):
-    """float32 [rows, cols] from N(0,1); a row is redrawn until all distinct."""
+    """float32 [rows, cols] from N(0,1) with no two equal values in a row:
+    entries that repeat an earlier value of their row are drawn again until
+    none does (at 2^18 values per row a float32 row has ~30 ties, so
+    redrawing whole rows would not terminate)."""
     g = rng(seed)
-    out = np.empty((rows, cols), dtype=np.float32)
+    out = g.standard_normal((rows, cols)).astype(np.float32)
     for r in range(rows):
+        row = out[r]
         while True:
-            v = g.standard_normal(cols).astype(np.float32)
-            if np.unique(v).size == cols:
-                out[r] = v
+            order = np.argsort(row, kind="stable")
+            srt = row[order]
+            dup = order[1:][srt[1:] == srt[:-1]]
+            if dup.size == 0:
                 break
+            row[dup] = g.standard_normal(dup.size).astype(np.float32)
     return out
 
 
