@@ -2,9 +2,11 @@
 """Benchmark of the MI355X sample sort.
 
 Default workload: 2^26 int32 keys (uniform, seeded, synthetic), keys only,
-random oversampling with p = 4096 buckets and oversampling s = 16, resident
-in HBM before the timed region.  One step = one full sort (sample, sample
-sort, splitters, classify, scan, stable scatter, bucket sorts).
+random oversampling with p = 256 buckets and oversampling s = 16, resident
+in HBM before the timed region.  One step = one full sort: per split level
+sample, sample sort, splitters, classify, scan and scatter, then the bucket
+sorts (with p = 256 each top bucket of ~2^18 keys is split once more, by the
+next level, before the bucket sorts).
 
 Prints ONE JSON line with Gkeys/s, the roofline of the dominant kernel
 (algorithmic bytes / its HIP-event time, against 8 TB/s HBM) and the CPU
@@ -26,6 +28,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of a kernel kind, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch), scaled by what the same counters read for a
+# plain device copy of the input in the same run (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0: the copy of 256 MiB reads 131,085 KiB and writes 262,144
+# KiB).  Valid only for the kernel sources and the workload they were taken
+# on; "traffic" is null for anything else.
+MEASURED_TRAFFIC = {
+    ("scatter", 26, 256, 16, "random", "uniform"): {
+        "src_sha256_16": "7bd8bef4e7af2614",
+        "bytes_per_launch": 582643917,   # mean of the two levels' launches: 596,475 and 541,501 KiB
+    },
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -34,7 +49,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sort", choices=["sort", "pairs", "segmented", "autograd"])
     ap.add_argument("--log2n", type=int, default=26)
-    ap.add_argument("--p", type=int, default=4096)
+    ap.add_argument("--p", type=int, default=256)
     ap.add_argument("--s", type=int, default=16)
     ap.add_argument("--sampling", default="random", choices=["random", "regular"])
     ap.add_argument("--dist", default="uniform")
@@ -73,18 +88,56 @@ def kernel_table(rep, steps):
 
 
 def roofline_of(rep, steps, bytes_per_step):
-    """Dominant kernel: the kind with the largest time; achieved = its
-    algorithmic bytes per step / its time per step."""
-    tot = {k: ms for k, (ms, c) in rep.items() if c}
-    dom = max(tot, key=tot.get)
-    t = tot[dom] / steps / 1e3
+    """Dominant kernel: the kind with the largest HIP-event time over the
+    timed region.  achieved = its algorithmic bytes per launch / its mean
+    launch duration (= bytes per step / time per step, summed over the
+    step's launches of that kind)."""
+    tot = {k: (ms, c) for k, (ms, c) in rep.items() if c}
+    dom = max(tot, key=lambda k: tot[k][0])
+    ms, c = tot[dom]
+    launches = c / steps
+    t = ms / steps / 1e3
     b = bytes_per_step.get(dom)
     if not b:
         return dom, None
     ach = b / t / 1e9
     return dom, {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                 "bytes_per_launch": b, "ms_per_launch": round(t * 1e3, 5)}
+                 "bytes_per_launch": int(b / launches), "launches_per_step": launches,
+                 "ms_per_launch": round(t * 1e3 / launches, 5)}
+
+
+def src_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1608_08648_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind, args):
+    t = MEASURED_TRAFFIC.get((kind, args.log2n, args.p, args.s, args.sampling, args.dist))
+    if t is None or args.tile or args.flags or t["src_sha256_16"] != src_hash():
+        return None
+    return t["bytes_per_launch"]
+
+
+def copy_rate(src, dst, reps=5):
+    """HBM rate of a plain device copy of the input (read + write bytes per
+    second); also the calibration kernel of the HBM traffic counters."""
+    import torch
+    dst.copy_(src)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return round(2 * src.numel() * src.element_size() / (ms / 1e3) / 1e9, 1)
 
 
 def bench_sort(args):
@@ -102,10 +155,21 @@ def bench_sort(args):
     prm = api.params(p=args.p, s=args.s, sampling=args.sampling, seed=1234, tile=args.tile, flags=args.flags)
     info = api.stage_layout(n, native.SS_I32, native.SS_V_NONE, prm)
     ws = api._workspace(api.workspace_size(n, native.SS_I32, native.SS_V_NONE, prm), dev)
+    copy_gbs = copy_rate(kd, out)
     for _ in range(args.warmup):
         api.sort_keys(kd, prm, out=out, ws=ws)
     torch.cuda.synchronize()
+    # per-kernel table: every launch bracketed by events (outside the timed
+    # region: the events themselves add a few microseconds per launch)
     native.profile_enable(True, max_launches=64 * (args.steps + 1))
+    for _ in range(args.steps):
+        api.sort_keys(kd, prm, out=out, ws=ws)
+    native.profile_collect()
+    table = native.profile_report()
+    dom = max((k for k in table if table[k][1]), key=lambda k: table[k][0])
+    # timed region: events only around the dominant kernel's launches
+    native.profile_enable(True, max_launches=64 * (args.steps + 1))
+    native.profile_kinds([dom])
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -119,11 +183,20 @@ def bench_sort(args):
     rep = native.profile_report()
     native.profile_enable(False)
     status = api.status(ws)
+    levels = api.level_stats(ws)
     got = out.cpu().numpy()
     ok = bool(np.all(got[1:] >= got[:-1])) and fingerprint(got) == fingerprint(keys)
+    # algorithmic bytes: every level reads its keys to count them (classify)
+    # and reads + writes them to split them (scatter); the bucket kernels
+    # read + write each key once
     kb = 4
-    bytes_per_step = {"classify": kb * n, "scatter": 2 * kb * n, "bucket_sort": 2 * kb * n}
+    split_keys = sum(lv["keys"] for lv in levels)
+    inplace = sum(lv["bucket_keys"] for lv in levels)
+    bytes_per_step = {"classify": kb * split_keys, "scatter": 2 * kb * split_keys,
+                      "bucket_sort": 2 * kb * inplace, "bucket_leftover": 2 * kb * (n - inplace)}
     dom, roof = roofline_of(rep, args.steps, bytes_per_step)
+    if roof is not None:
+        roof["traffic"] = measured_traffic(dom, args)
     gk = n / (ms / 1e3) / 1e9
     res = {
         "metric": "Gkeys/s and % of HBM roofline, sample sort 2^26 int32; batched vs per-segment",
@@ -133,9 +206,12 @@ def bench_sort(args):
         "config": {"workload": f"sample sort of 2^{args.log2n} int32 keys ({args.dist}), keys only",
                    "n": n, "p": args.p, "p_eff": info.p_eff, "s": args.s, "sampling": args.sampling,
                    "levels_below_top": info.levels, "dist": args.dist, "seed": seed, "flags": args.flags},
-        "hbm_frac_20B_per_key": round(gk * 20 / HBM_PEAK_GBS, 4),
+        "sort_bytes_per_key": round(sum(bytes_per_step.values()) / n, 3),
+        "sort_frac_of_hbm": round(gk * sum(bytes_per_step.values()) / n / HBM_PEAK_GBS, 4),
         "roofline": roof,
-        "kernels": kernel_table(rep, args.steps),
+        "copy_GBs": copy_gbs,
+        "levels": levels,
+        "kernels": kernel_table(table, args.steps),
         "check": "sorted+multiset" if ok else "FAILED",
         "device_status": status,
     }

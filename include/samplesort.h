@@ -57,9 +57,6 @@ enum { SS_RANDOM = 0,   /* Alg. 2: p*s-1 keys drawn uniformly (with replacement)
 #define SS_F_NO_RECURSION   4u  /* plan no split level below the top one: a bucket too large for
                                    one work-group is then sorted by a one-work-group merge sort
                                    (slow; for tests of that path) */
-#define SS_F_RECLASSIFY     8u  /* keys only: the split pass classifies every key again instead of
-                                   reading the bucket indices the counting pass stored (less
-                                   workspace, more arithmetic) */
 
 /* return codes */
 enum { SS_OK = 0, SS_EINVAL = -1, SS_EWORKSPACE = -2, SS_EHIP = -3, SS_EDEVICE = -4 };
@@ -172,6 +169,28 @@ int ss_scatter_grad(const void *grad_y, const int64_t *perm, void *grad_x, size_
  * message names it). */
 int ss_status(const void *ws, void *stream);
 
+/* Split levels.  A bucket that the in-work-group bucket sorts cannot take
+ * (Lemma 1 bounds its size only in expectation-scaled terms, and a skewed
+ * input can exceed any fixed capacity) is sample-sorted again, by the next
+ * level, with its own sample and splitters; level 0 splits the whole input
+ * (or, for segmented_sort, the segments too long for one work-group). */
+#define SS_MAX_LEVELS 6
+
+typedef struct {
+  uint32_t segments;     /* segments the level split */
+  uint32_t buckets;      /* buckets they were split into */
+  uint64_t keys;         /* keys in those segments */
+  uint64_t bucket_keys;  /* of those, keys that the level's bucket kernel sorted in place;
+                            the rest went to the next level or to the larger-bucket sorts */
+} ss_level_info;
+
+/* Wait for `stream`, then fill *info with the counts of split level `level`
+ * (0 <= level < SS_MAX_LEVELS) of the last call that used `ws` (a
+ * diagnostic: how deep the recursion went and how much data each level
+ * moved).  Levels the call did not reach read as zero.  SS_EINVAL for a
+ * NULL pointer or a level out of range. */
+int ss_level_stats(const void *ws, int level, ss_level_info *info, void *stream);
+
 /* Per-kernel timing, for benchmarks.  While enabled (on != 0), every kernel
  * the library launches is bracketed by two HIP events recorded on the
  * caller's stream (from a pool of `max_launches` event pairs created here;
@@ -180,8 +199,11 @@ int ss_status(const void *ws, void *stream);
  * adds their durations to per-kernel totals; ss_profile_report(i, ...)
  * returns the name, total milliseconds and launch count of kernel kind i
  * (SS_EINVAL past the last kind).  ss_profile_enable(0) frees the pool and
- * clears the totals. */
+ * clears the totals.  ss_profile_kinds(mask) limits the bracketing to the
+ * kinds whose bit (1 << i) is set (every kind after ss_profile_enable), so
+ * that a timed run records events only around the kernels it measures. */
 int ss_profile_enable(int on, int max_launches);
+int ss_profile_kinds(unsigned kind_mask);
 int ss_profile_collect(void);
 int ss_profile_report(int kind, const char **name, double *total_ms, uint64_t *launches);
 

@@ -184,6 +184,21 @@ def status(ws, stream=None):
     return N.last_error()
 
 
+def level_stats(ws, stream=None):
+    """Per split level of the last call on ws: dicts of segments, buckets,
+    keys (split input) and bucket_keys (sorted in place by the level's
+    bucket kernel), for the levels the call reached."""
+    out = []
+    for lv in range(N.SS_MAX_LEVELS):
+        info = N.LevelInfo()
+        N.check(N.lib().ss_level_stats(_ptr(ws), lv, ctypes.byref(info), _stream(stream)))
+        if info.segments == 0:
+            break
+        out.append({"segments": info.segments, "buckets": info.buckets, "keys": info.keys,
+                    "bucket_keys": info.bucket_keys})
+    return out
+
+
 def stages(keys, prm, key_type=None):
     """Run sort_keys with the stage export on and return (sorted keys, dict of
     the top-level sorted sample, splitters and bucket counts, StageInfo)."""

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -50,6 +51,7 @@ const char* const PROF_NAMES[PK_COUNT] = {
 
 struct Prof {
   bool on = false;
+  uint32_t mask = ~0u;              // kinds that get events
   int cap = 0, used = 0;
   std::vector<hipEvent_t> ev;       // 2 per launch
   std::vector<int> kind;
@@ -63,7 +65,7 @@ struct ProfScope {
   int slot = -1;
   hipStream_t st;
   ProfScope(int k, hipStream_t s) : st(s) {
-    if (!g_prof.on || g_prof.used >= g_prof.cap) return;
+    if (!g_prof.on || !((g_prof.mask >> k) & 1u) || g_prof.used >= g_prof.cap) return;
     slot = g_prof.used++;
     g_prof.kind[slot] = k;
     hipEventRecord(g_prof.ev[2 * slot], st);
@@ -148,7 +150,7 @@ uint32_t p_effective(uint64_t n, uint32_t p, uint32_t s, int mode) {
 // every key width).
 constexpr uint32_t TILE_UNIT = 8192;
 uint32_t default_tile(uint32_t p) {
-  uint64_t t = std::max<uint64_t>(16384, 16ull * p);
+  uint64_t t = std::max<uint64_t>(65536, 16ull * p);
   return (uint32_t)(cdiv(t, TILE_UNIT) * TILE_UNIT);
 }
 
@@ -173,6 +175,9 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
                  uint64_t m0, uint64_t est_max0, uint32_t s, uint32_t p_cap, uint32_t tile_req, bool recurse,
                  LevelsPlan* P) {
   const uint32_t C = small_cap(ty.KW, ty.VW);
+  // buckets larger than this go one level down when there is a level below
+  // (keys only: beyond the slot sort's capacity)
+  const uint32_t Cpush = ty.VW == 0 ? slot_cap(ty.KW) : C;
   const uint32_t Cs = sample_cap(ty.KW);
   const double f = spread(s);
   // automatically sized buckets aim at about half of what the bucket sort
@@ -199,8 +204,8 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
       lv.p_cap = p_cap;
       lv.pmax = p_cap > 256 ? 4096 : 256;
       lv.tile = tile_req ? (uint32_t)(cdiv(tile_req, TILE_UNIT) * TILE_UNIT) : default_tile(p_cap);
-      uint64_t sc = (l == 0) ? seg_cap0 : std::min<uint64_t>(P->lv[l - 1].bkt_cap, N / (C + 1) + 1);
-      sc = std::min<uint64_t>(sc, N / (C + 1) + 1);
+      uint64_t sc = (l == 0) ? seg_cap0 : std::min<uint64_t>(P->lv[l - 1].bkt_cap, N / (Cpush + 1) + 1);
+      sc = std::min<uint64_t>(sc, N / (Cpush + 1) + 1);
       lv.seg_cap = (uint32_t)std::max<uint64_t>(sc, 1);
       lv.tiles_cap = N / lv.tile + lv.seg_cap + 1;
       lv.bkt_cap = std::min<uint64_t>((uint64_t)lv.seg_cap * p_cap, 2 * N / target + 2ull * lv.seg_cap + 2);
@@ -225,17 +230,11 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
       P->o_stag2 = L.take(4 * m0);
     }
     P->nlev = l + 1;
-    if (!recurse || est <= C) break;
+    // the top level of a single sort has a caller-chosen p, so its buckets
+    // may well exceed the slot sort; deeper levels pick p for the target
+    // size, and only a rare tail exceeds it: those take the radix sort
+    if (!recurse || est <= ((l == 0 && p0) ? Cpush : C)) break;
   }
-}
-
-// Bytes of the bucket-index buffer: a tile-sized slice per tile of the
-// level with the most tiles, 2 bytes per key (1 when p <= 256).
-uint64_t ids_bytes(const LevelsPlan& lp) {
-  uint64_t b = 0;
-  for (int l = 0; l < lp.nlev; l++)
-    b = std::max<uint64_t>(b, lp.lv[l].tiles_cap * lp.lv[l].tile * (lp.lv[l].pmax > 256 ? 2 : 1));
-  return b;
 }
 
 // Full plan of one call.
@@ -251,7 +250,7 @@ struct Plan {
   uint64_t m = 0;
   bool regular = false;
   LevelsPlan lp;
-  size_t o_ctl = 0, o_tmp = 0, o_vtmp = 0, o_ids = 0;
+  size_t o_ctl = 0, o_tmp = 0, o_vtmp = 0;
   size_t o_exp_so = 0, o_exp_st = 0, o_exp_po = 0, o_exp_pt = 0, o_exp_cnt = 0;
   bool exp = false;
   size_t o_small = 0;      // segmented: small-segment list
@@ -328,7 +327,6 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   P->o_vtmp = ty.VW ? L.take((size_t)ty.VW * n) : 0;
   const bool recurse = !(prm.flags & SS_F_NO_RECURSION);
   plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp);
-  if (ty.VW == 0 && !(prm.flags & SS_F_RECLASSIFY)) P->o_ids = L.take(ids_bytes(P->lp));
   if (P->regular) {
     // blocks sorted with their in-block index as payload (Alg. 1 step 1)
     P->o_regk = L.take((size_t)ty.KW * n);
@@ -373,7 +371,6 @@ int plan_segmented(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, cons
     uint64_t seg_cap0 = std::min<uint64_t>(nseg, total / (C + 1) + 1);
     const bool recurse = !(prm.flags & SS_F_NO_RECURSION);
     plan_levels(L, ty, total, seg_cap0, maxlen, 0, 0, 0, prm.s, p_cap, prm.tile, recurse, &P->lp);
-    if (ty.VW == 0 && !(prm.flags & SS_F_RECLASSIFY)) P->o_ids = L.take(ids_bytes(P->lp));
   }
   P->bytes = L.cur;
   return SS_OK;
@@ -440,7 +437,6 @@ LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void*
   a.hist = (uint32_t*)(ws + lv.o_hist);
   a.scan_part = (uint32_t*)(ws + lv.o_part);
   a.left = (SmallEnt*)(ws + lv.o_left);
-  a.ids = P.o_ids ? (void*)(ws + P.o_ids) : nullptr;
   a.nleft = &g->nleft[l];
   if (P.exp && l == 0) {
     a.exp_smp_ord = (uint64_t*)(ws + P.o_exp_so);
@@ -520,7 +516,9 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       LAUNCH_CHECK();
       LAUNCH(PK_BUCKET_SORT, (k_bucket_sort_keys<KW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a, exp);
       LAUNCH_CHECK();
-      LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<KW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a);
+      // few buckets are handed on: a small grid walks the list
+      LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<KW>), dim3((uint32_t)std::min<uint64_t>(lv.bkt_cap, 512)),
+             dim3(NT), 0, st, a);
     } else {
       if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
       else LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 256>), dim3(tiles), dim3(NT), 0, st, a);
@@ -799,6 +797,12 @@ int ss_profile_enable(int on, int max_launches) {
   return SS_OK;
 }
 
+int ss_profile_kinds(unsigned kind_mask) {
+  g_err[0] = 0;
+  g_prof.mask = kind_mask;
+  return SS_OK;
+}
+
 int ss_profile_collect(void) {
   g_err[0] = 0;
   for (int i = 0; i < g_prof.used; i++) {
@@ -817,6 +821,23 @@ int ss_profile_report(int kind, const char** name, double* total_ms, uint64_t* l
   if (name) *name = PROF_NAMES[kind];
   if (total_ms) *total_ms = g_prof.total[kind];
   if (launches) *launches = g_prof.count[kind];
+  return SS_OK;
+}
+
+static_assert(MAX_LEVELS == SS_MAX_LEVELS, "level count of the ABI");
+
+int ss_level_stats(const void* ws, int level, ss_level_info* info, void* stream) {
+  g_err[0] = 0;
+  if (!ws || !info) return fail(SS_EINVAL, "ws or info is NULL");
+  if (level < 0 || level >= MAX_LEVELS) return fail(SS_EINVAL, "level %d outside [0, %d)", level, MAX_LEVELS);
+  HIP_TRY(hipStreamSynchronize(as_stream(stream)));
+  LevelCtl c;
+  HIP_TRY(hipMemcpy(&c, (const char*)ws + offsetof(Ctl, lv) + sizeof(LevelCtl) * level, sizeof c,
+                    hipMemcpyDeviceToHost));
+  info->segments = c.nsegs;
+  info->buckets = c.total_buckets;
+  info->keys = c.keys;
+  info->bucket_keys = c.bucket_keys;
   return SS_OK;
 }
 

@@ -80,6 +80,8 @@ struct LevelCtl {
   uint64_t total_hist;
   uint32_t total_tree;
   uint32_t max_m;
+  uint64_t keys;          // keys in the level's segments (the input of its split)
+  uint64_t bucket_keys;   // keys its bucket kernel sorted in place (not handed on)
 };
 
 struct SmallEnt { uint64_t beg; uint32_t len; uint32_t pad; };
@@ -128,7 +130,6 @@ struct LevelArgs {
   uint64_t* exp_spl_ord;
   uint64_t* exp_spl_tag;
   uint64_t* exp_counts;
-  void* ids;               // bucket of every key, written by k_classify for k_scatter_keys (or null)
   SmallEnt* left;          // buckets handed from the slot sort to the radix sort (keys only)
   uint32_t* nleft;
   uint32_t tile;           // keys per tile in the split passes
@@ -167,14 +168,12 @@ __device__ __forceinline__ uint64_t derive_seed(uint64_t seed, uint32_t depth, u
   return sm64_mix(seed ^ sm64_mix(((uint64_t)depth << 32) + bucket));
 }
 
-// stored bucket index of a key: one byte when p <= 256
-template <int PMAX> struct BucketId { using T = typename std::conditional<(PMAX <= 256), uint8_t, uint16_t>::type; };
-// Keys move through classify and the keys-only split in blocks of
-// IdBlock::U * NT keys: thread t takes keys i0 + u*NT + t (coalesced), and
-// stores their U bucket indices contiguously at ids[tile base + i0 + t*U + u]
-// (one wide store / load per thread).  Tiles are multiples of the block.
-template <typename T, int U> struct alignas(sizeof(T) * U) IdVec { T x[U]; };
-template <int KW> struct IdBlock { static constexpr int U = KW == 4 ? 16 : 8; static constexpr int B = U * NT; };
+// Keys in flight per thread in the counting and split passes.
+// (halved in the split for p > 256, whose per-bucket counters and tree fill the LDS)
+template <int KW, int PMAX = 256> struct SplitU {
+  static constexpr int U = (KW == 4 ? 16 : 8) / (PMAX > 256 ? 2 : 1);
+  static constexpr int CH = U * NT;
+};
 
 // search tree in LDS: 4-byte keys as packed u64, 8-byte keys as (ord, tag)
 template <int KW, int PMAX>
@@ -409,7 +408,7 @@ __global__ void __launch_bounds__(NT) k_plan(LevelArgs a, uint32_t samp_cap) {
   __shared__ uint32_t sh32[NT / WAVE + 2];
   const uint32_t n = min(a.ctl->nsegs, a.seg_cap);
   uint32_t run_s = 0, run_t = 0, run_b = 0, max_m = 0;
-  uint64_t run_h = 0;
+  uint64_t run_h = 0, run_k = 0;
   for (uint32_t base = 0; base < n; base += NT) {
     const uint32_t i = base + threadIdx.x;
     uint32_t m = 0, nt = 0, p = 0;
@@ -442,6 +441,8 @@ __global__ void __launch_bounds__(NT) k_plan(LevelArgs a, uint32_t samp_cap) {
     const uint32_t to = block_excl_scan<NT>(nt, sh32, &tt);
     const uint32_t bo = block_excl_scan<NT>(p, sh32, &tb);
     const uint64_t ho = block_excl_scan<NT, uint64_t>(h, sh64, &th);
+    uint64_t tk;
+    block_excl_scan<NT, uint64_t>(i < n ? (uint64_t)d.len : 0ull, sh64, &tk);
     const uint32_t wm = wave_max(m);
     if (lane_id() == 0) sh32[wave_id()] = wm;
     __syncthreads();
@@ -459,6 +460,7 @@ __global__ void __launch_bounds__(NT) k_plan(LevelArgs a, uint32_t samp_cap) {
     run_t += tt;
     run_b += tb;
     run_h += th;
+    run_k += tk;
   }
   if (threadIdx.x == 0) {
     a.ctl->nsegs = n;
@@ -468,6 +470,8 @@ __global__ void __launch_bounds__(NT) k_plan(LevelArgs a, uint32_t samp_cap) {
     a.ctl->total_tree = run_b;
     a.ctl->total_hist = run_h;
     a.ctl->max_m = max_m;
+    a.ctl->keys = run_k;
+    a.ctl->bucket_keys = 0;
   }
 }
 
@@ -693,11 +697,41 @@ __global__ void __launch_bounds__(256) k_sample_regular(LevelArgs a, const void*
 }
 
 // Per-tile bucket counts (step 4), stored bucket-major per segment:
-// hist[hist_off + b * ntiles + tile].
+// hist[hist_off + b * ntiles + tile].  Each thread classifies U keys at a
+// time (their tree walks advance level by level together) and adds runs of
+// equal buckets to an LDS histogram.
+template <int KW, int PMAX>
+__device__ __forceinline__ void count_block(const LevelArgs& a, const TreeLds<KW, PMAX>& tr, const SegDesc& d,
+                                            const typename KeyOf<KW>::T* src, uint32_t i0, uint32_t t1, bool full,
+                                            uint32_t* cnt, uint32_t& cur, uint32_t& run) {
+  using KT = typename KeyOf<KW>::T;
+  constexpr int U = SplitU<KW>::U;
+  KT key[U];
+  uint32_t tag[U], b[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    uint32_t i = i0 + u * NT + threadIdx.x;
+    tag[u] = i;
+    key[u] = (full || i < t1) ? to_ord(src[i], a.kin) : KT(0);
+  }
+  tr.template classify_many<U>(key, tag, d.lgp, d.p, b);
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    if (full || i0 + u * NT + threadIdx.x < t1) {
+      if (b[u] != cur) {
+        if (run) atomicAdd(&cnt[cur], run);
+        cur = b[u];
+        run = 0;
+      }
+      run++;
+    }
+  }
+}
+
 template <int KW, int PMAX>
 __global__ void __launch_bounds__(NT) k_classify(LevelArgs a) {
   using KT = typename KeyOf<KW>::T;
-  using IdT = typename BucketId<PMAX>::T;
+  constexpr int CH = SplitU<KW>::CH;
   __shared__ TreeLds<KW, PMAX> tr;
   __shared__ uint32_t cnt[PMAX];
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -713,36 +747,15 @@ __global__ void __launch_bounds__(NT) k_classify(LevelArgs a) {
   const uint32_t t1 = min(t0 + a.tile, d.len);
   const KT* src = (const KT*)a.src + d.beg;
   uint32_t cur = ~0u, run = 0;
-  constexpr int U = IdBlock<KW>::U;   // keys per thread in flight
-  IdT* tile_ids = a.ids ? (IdT*)a.ids + (uint64_t)tile * a.tile : nullptr;
-  for (uint32_t i0 = t0; i0 < t1; i0 += U * NT) {
-    KT key[U];
-    uint32_t tag[U], b[U];
+  uint32_t i0 = t0;
+  for (; i0 + CH <= t1; i0 += CH) {
+    if (i0 + 2 * CH <= t1) {   // start fetching the next block (lands in L2 / L1)
 #pragma unroll
-    for (int u = 0; u < U; u++) {
-      uint32_t i = i0 + u * NT + threadIdx.x;
-      tag[u] = i;
-      key[u] = i < t1 ? to_ord(src[i], a.kin) : KT(0);
+      for (int u = 0; u < SplitU<KW>::U; u += 4) __builtin_prefetch(&src[i0 + CH + u * NT + threadIdx.x]);
     }
-    tr.template classify_many<U>(key, tag, d.lgp, d.p, b);
-    if (tile_ids) {
-      IdVec<IdT, U> v;
-#pragma unroll
-      for (int u = 0; u < U; u++) v.x[u] = (IdT)b[u];
-      *(IdVec<IdT, U>*)(tile_ids + (i0 - t0) + threadIdx.x * U) = v;
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      if (i0 + u * NT + threadIdx.x < t1) {
-        if (b[u] != cur) {
-          if (run) atomicAdd(&cnt[cur], run);
-          cur = b[u];
-          run = 0;
-        }
-        run++;
-      }
-    }
+    count_block<KW, PMAX>(a, tr, d, src, i0, t1, true, cnt, cur, run);
   }
+  if (i0 < t1) count_block<KW, PMAX>(a, tr, d, src, i0, t1, false, cnt, cur, run);
   if (run) atomicAdd(&cnt[cur], run);
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < d.p; b += NT) a.hist[d.hist_off + (uint64_t)b * d.ntiles + tw] = cnt[b];
@@ -959,6 +972,7 @@ __global__ void __launch_bounds__(NT) k_bucket_sort(LevelArgs a, int export_stag
   const uint64_t gb = d.beg + st;
   if (sz <= C) {
     sort_small<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, gb, sz, 0, 0, a.kout, sm);
+    if (threadIdx.x == 0) atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)sz);
     return;
   }
   bucket_overflow<KW, VW>(a, d, b, gb, sz, sm);
@@ -973,28 +987,96 @@ __global__ void __launch_bounds__(NT) k_bucket_sort(LevelArgs a, int export_stag
 // instead of a stable ranking.
 
 // Split: every key goes to its bucket's region for this tile.  Each chunk
-// is grouped by bucket in LDS (slots reserved with LDS atomics), then every
-// bucket's run is written out contiguously.
+// of U*NT keys is grouped by bucket in LDS (slots reserved with LDS
+// atomics), then every bucket's run is written out contiguously.  Per-bucket
+// chunk counters alternate between two sets so a chunk needs three barriers:
+// after counting, after the scan, after grouping.
 template <int KW, int PMAX>
 struct ScatterKeysLds {
   using KT = typename KeyOf<KW>::T;
-  static constexpr int CH = IdBlock<KW>::B;   // keys per chunk
-  TreeLds<KW, PMAX> tr;    // used only when no stored bucket indices are given
-  uint32_t gofs[PMAX];     // next free in-segment position of each bucket
-  uint32_t ccnt[PMAX];     // chunk count, then running slot of each bucket
-  uint32_t cst[PMAX];      // chunk start of each bucket
-  KT sk[CH];               // chunk keys grouped by bucket
-  uint16_t sb[CH];         // their buckets
+  using BT = typename std::conditional<(PMAX <= 256), uint8_t, uint16_t>::type;
+  static constexpr int CH = SplitU<KW, PMAX>::CH;
+  TreeLds<KW, PMAX> tr;
+  uint32_t gofs[PMAX];      // in-segment position of each bucket's run for the current chunk
+  uint32_t cur[2][PMAX];    // chunk counts, then cursors (alternating chunks)
+  uint32_t cst[2][PMAX];    // chunk start of each bucket (alternating chunks)
+  KT sk[CH];                // chunk keys grouped by bucket
+  BT sb[CH];                // their buckets
   alignas(8) uint32_t red[32];
 };
+
+template <int KW, int PMAX, bool FULL>
+__device__ __forceinline__ void split_chunk(const LevelArgs& a, const SegDesc& d, ScatterKeysLds<KW, PMAX>& sm,
+                                            const typename KeyOf<KW>::T* src, typename KeyOf<KW>::T* dst,
+                                            uint32_t c0, uint32_t cn, int x, bool first) {
+  using KT = typename KeyOf<KW>::T;
+  using BT = typename ScatterKeysLds<KW, PMAX>::BT;
+  constexpr int U = SplitU<KW, PMAX>::U;
+  constexpr int CH = SplitU<KW, PMAX>::CH;
+  const int t = threadIdx.x;
+  KT key[U];
+  uint32_t tag[U], b[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    uint32_t i = u * NT + t;
+    tag[u] = c0 + i;
+    key[u] = (FULL || i < cn) ? to_ord(src[c0 + i], a.kin) : KT(0);
+  }
+  sm.tr.template classify_many<U>(key, tag, d.lgp, d.p, b);
+#pragma unroll
+  for (int u = 0; u < U; u++)
+    if (FULL || (uint32_t)(u * NT + t) < cn) atomicAdd(&sm.cur[x][b[u]], 1u);
+  __syncthreads();
+  // close the previous chunk's bookkeeping, then chunk starts of this one
+  {
+    constexpr int PER = (PMAX + NT - 1) / NT;
+    const int o = x ^ 1;
+    uint32_t v[PER], sum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      uint32_t bb = t * PER + j;
+      v[j] = 0;
+      if (bb < d.p) {
+        if (!first) {
+          sm.gofs[bb] += sm.cur[o][bb] - sm.cst[o][bb];
+          sm.cur[o][bb] = 0;
+        }
+        v[j] = sm.cur[x][bb];
+      }
+      sum += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<NT>(sum, sm.red, &tot);
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      uint32_t bb = t * PER + j;
+      if (bb < d.p) { sm.cst[x][bb] = run; sm.cur[x][bb] = run; }
+      run += v[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    if (FULL || (uint32_t)(u * NT + t) < cn) {
+      uint32_t pos = atomicAdd(&sm.cur[x][b[u]], 1u);
+      sm.sk[pos] = key[u];
+      sm.sb[pos] = (BT)b[u];
+    }
+  }
+  __syncthreads();
+  const uint32_t lim = FULL ? (uint32_t)CH : cn;
+#pragma unroll 4
+  for (uint32_t j = t; j < lim; j += NT) {
+    uint32_t bb = sm.sb[j];
+    dst[sm.gofs[bb] + (j - sm.cst[x][bb])] = sm.sk[j];
+  }
+}
 
 template <int KW, int PMAX>
 __global__ void __launch_bounds__(NT) k_scatter_keys(LevelArgs a) {
   using KT = typename KeyOf<KW>::T;
-  using IdT = typename BucketId<PMAX>::T;
   using L = ScatterKeysLds<KW, PMAX>;
   constexpr int CH = L::CH;
-  constexpr int U = CH / NT;
   __shared__ L sm;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const LevelCtl c = *a.ctl;
@@ -1003,82 +1085,24 @@ __global__ void __launch_bounds__(NT) k_scatter_keys(LevelArgs a) {
   const SegDesc d = a.segs[si];
   const uint32_t tw = tile - d.tile_off;
   const int t = threadIdx.x;
-  if (!a.ids) sm.tr.load(a.tree, a.tree_tag, d.tree_off, d.p);
+  sm.tr.load(a.tree, a.tree_tag, d.tree_off, d.p);
   const uint32_t base = a.hist[d.hist_off];
   for (uint32_t b = t; b < d.p; b += NT) {
     sm.gofs[b] = a.hist[d.hist_off + (uint64_t)b * d.ntiles + tw] - base;
-    sm.ccnt[b] = 0;
+    sm.cur[0][b] = 0;
+    sm.cur[1][b] = 0;
   }
   __syncthreads();
   const uint32_t t0 = tw * a.tile;
   const uint32_t t1 = min(t0 + a.tile, d.len);
   const KT* src = (const KT*)a.src + d.beg;
-  const IdT* tile_ids = a.ids ? (const IdT*)a.ids + (uint64_t)tile * a.tile : nullptr;   // from k_classify
   KT* dst = (KT*)a.dst + d.beg;
-  for (uint32_t c0 = t0; c0 < t1; c0 += CH) {
-    const uint32_t cn = min((uint32_t)CH, t1 - c0);
-    KT key[U];
-    uint32_t b[U];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      uint32_t i = u * NT + t;
-      key[u] = i < cn ? to_ord(src[c0 + i], a.kin) : KT(0);
-    }
-    if (tile_ids) {
-      IdVec<IdT, U> v = *(const IdVec<IdT, U>*)(tile_ids + (c0 - t0) + t * U);
-#pragma unroll
-      for (int u = 0; u < U; u++) b[u] = v.x[u];
-    } else {
-      uint32_t tag[U];
-#pragma unroll
-      for (int u = 0; u < U; u++) tag[u] = c0 + u * NT + t;
-      sm.tr.template classify_many<U>(key, tag, d.lgp, d.p, b);
-    }
-#pragma unroll
-    for (int u = 0; u < U; u++)
-      if ((uint32_t)(u * NT + t) < cn) atomicAdd(&sm.ccnt[b[u]], 1u);
-    __syncthreads();
-    // chunk starts (exclusive scan over the buckets); counters become cursors
-    {
-      constexpr int PER = (PMAX + NT - 1) / NT;
-      uint32_t v[PER], sum = 0;
-#pragma unroll
-      for (int j = 0; j < PER; j++) {
-        uint32_t bb = t * PER + j;
-        v[j] = bb < d.p ? sm.ccnt[bb] : 0u;
-        sum += v[j];
-      }
-      uint32_t tot;
-      uint32_t run = block_excl_scan<NT>(sum, sm.red, &tot);
-#pragma unroll
-      for (int j = 0; j < PER; j++) {
-        uint32_t bb = t * PER + j;
-        if (bb < d.p) { sm.cst[bb] = run; sm.ccnt[bb] = run; }
-        run += v[j];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      if ((uint32_t)(u * NT + t) < cn) {
-        uint32_t pos = atomicAdd(&sm.ccnt[b[u]], 1u);
-        sm.sk[pos] = key[u];
-        sm.sb[pos] = (uint16_t)b[u];
-      }
-    }
-    __syncthreads();
-    // runs out, in order
-    for (uint32_t j = t; j < cn; j += NT) {
-      uint32_t bb = sm.sb[j];
-      dst[sm.gofs[bb] + (j - sm.cst[bb])] = sm.sk[j];
-    }
-    __syncthreads();
-    for (uint32_t bb = t; bb < d.p; bb += NT) {
-      sm.gofs[bb] += sm.ccnt[bb] - sm.cst[bb];
-      sm.ccnt[bb] = 0;
-    }
-    __syncthreads();
-  }
+  uint32_t c0 = t0;
+  int x = 0;
+  bool first = true;
+  for (; c0 + CH <= t1; c0 += CH, x ^= 1, first = false)
+    split_chunk<KW, PMAX, true>(a, d, sm, src, dst, c0, CH, x, first);
+  if (c0 < t1) split_chunk<KW, PMAX, false>(a, d, sm, src, dst, c0, t1 - c0, x, first);
 }
 
 // Bucket sort of one bucket by counting into S value slots: slot(key) =
@@ -1254,8 +1278,29 @@ __global__ void __launch_bounds__(NT) k_bucket_sort_keys(LevelArgs a, int export
   const KT lo = lo_k ? spl_key(b) : KT(0);
   const KT hi = hi_k ? spl_key(b + 1) : KT(0);
   if (sz <= (uint32_t)SlotLds<KW>::C &&
-      slot_sort<KW>((const KT*)a.dst, (KT*)a.out, gb, sz, 0, a.kout, sm, lo_k, lo, hi_k, hi))
+      slot_sort<KW>((const KT*)a.dst, (KT*)a.out, gb, sz, 0, a.kout, sm, lo_k, lo, hi_k, hi)) {
+    if (threadIdx.x == 0) atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)sz);
     return;
+  }
+  if (sz > (uint32_t)SlotLds<KW>::C && a.next_segs) {   // larger than the slot sort takes: split it again
+    if (threadIdx.x == 0) {
+      uint32_t slot = atomicAdd(&a.next_ctl->nsegs, 1u);
+      if (slot < a.next_cap) {
+        SegDesc nd = {};
+        nd.beg = gb;
+        nd.len = sz;
+        nd.seed = derive_seed(d.seed, d.depth + 1, b);
+        nd.depth = d.depth + 1;
+        nd.parent_bkt = b;
+        a.next_segs[slot] = nd;
+      } else {
+        atomicOr(&a.gctl->status, ST_LIST_FULL);
+        uint32_t k = atomicAdd(a.nleft, 1u);
+        a.left[k] = SmallEnt{gb, sz, x};
+      }
+    }
+    return;
+  }
   if (threadIdx.x == 0) {
     // (bucket index kept in pad: the next level derives its seed from it)
     uint32_t k = atomicAdd(a.nleft, 1u);
@@ -1270,16 +1315,19 @@ __global__ void __launch_bounds__(NT) k_bucket_leftover_keys(LevelArgs a) {
   using KT = typename KeyOf<KW>::T;
   constexpr uint32_t C = SmallCap<KW, 0>::C;
   __shared__ SmallLds<KW, 0, SmallCap<KW, 0>::KMAX> sm;
-  if (blockIdx.x >= *a.nleft) return;
-  const SmallEnt e = a.left[blockIdx.x];
-  if (e.len <= C) {
-    sort_small<KW, 0>((const KT*)a.dst, nullptr, (KT*)a.out, nullptr, e.beg, e.len, 0, 0, a.kout, sm);
-    return;
+  const uint32_t nl = *a.nleft;
+  for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+    const SmallEnt e = a.left[li];
+    if (e.len <= C) {
+      sort_small<KW, 0>((const KT*)a.dst, nullptr, (KT*)a.out, nullptr, e.beg, e.len, 0, 0, a.kout, sm);
+      continue;
+    }
+    const LevelCtl c = *a.ctl;
+    const uint32_t si = find_seg(a.segs, c.nsegs, e.pad, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
+    const SegDesc d = a.segs[si];
+    bucket_overflow<KW, 0>(a, d, e.pad - d.bkt_off, e.beg, e.len, sm);
+    __syncthreads();
   }
-  const LevelCtl c = *a.ctl;
-  const uint32_t si = find_seg(a.segs, c.nsegs, e.pad, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
-  const SegDesc d = a.segs[si];
-  bucket_overflow<KW, 0>(a, d, e.pad - d.bkt_off, e.beg, e.len, sm);
 }
 
 // ------------------------------------------------- entry kernels

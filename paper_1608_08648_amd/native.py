@@ -19,14 +19,14 @@ SS_RANDOM, SS_REGULAR = 0, 1
 SS_F_EXPORT_STAGES = 1
 SS_F_FORCE_PIPELINE = 2
 SS_F_NO_RECURSION = 4
-SS_F_RECLASSIFY = 8
 # return codes
 SS_OK, SS_EINVAL, SS_EWORKSPACE, SS_EHIP, SS_EDEVICE = 0, -1, -2, -3, -4
 SS_P_MAX = 4096
+SS_MAX_LEVELS = 6
 
 EXPORTS = ("ss_last_error", "ss_workspace_size", "ss_stage_layout", "sample_sort_keys", "sample_sort_pairs",
-           "ss_segmented_workspace_size", "segmented_sort", "ss_scatter_grad", "ss_status",
-           "ss_profile_enable", "ss_profile_collect", "ss_profile_report")
+           "ss_segmented_workspace_size", "segmented_sort", "ss_scatter_grad", "ss_status", "ss_level_stats",
+           "ss_profile_enable", "ss_profile_kinds", "ss_profile_collect", "ss_profile_report")
 
 
 class Params(ctypes.Structure):
@@ -40,6 +40,11 @@ class StageInfo(ctypes.Structure):
                 ("sample_ord", ctypes.c_uint64), ("sample_tag", ctypes.c_uint64), ("spl_ord", ctypes.c_uint64),
                 ("spl_tag", ctypes.c_uint64), ("counts", ctypes.c_uint64), ("direct", ctypes.c_uint32),
                 ("levels", ctypes.c_uint32)]
+
+
+class LevelInfo(ctypes.Structure):
+    _fields_ = [("segments", ctypes.c_uint32), ("buckets", ctypes.c_uint32), ("keys", ctypes.c_uint64),
+                ("bucket_keys", ctypes.c_uint64)]
 
 
 class SortError(RuntimeError):
@@ -71,7 +76,9 @@ def lib():
         L.segmented_sort.argtypes = [P, P, P, P, P, SZ, SZ, SZ, I, I, PP, P, SZ, P]
         L.ss_scatter_grad.argtypes = [P, P, P, SZ, SZ, I, P]
         L.ss_status.argtypes = [P, P]
+        L.ss_level_stats.argtypes = [P, I, ctypes.POINTER(LevelInfo), P]
         L.ss_profile_enable.argtypes = [I, I]
+        L.ss_profile_kinds.argtypes = [ctypes.c_uint]
         L.ss_profile_collect.argtypes = []
         L.ss_profile_report.argtypes = [I, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_uint64)]
@@ -94,6 +101,25 @@ def last_error():
 
 def profile_enable(on, max_launches=4096):
     check(lib().ss_profile_enable(1 if on else 0, max_launches))
+
+
+def profile_kinds(names=None):
+    """Bracket only the named kernel kinds (None: every kind)."""
+    if names is None:
+        check(lib().ss_profile_kinds(0xFFFFFFFF))
+        return
+    idx = {}
+    i = 0
+    while True:
+        name = ctypes.c_char_p()
+        if lib().ss_profile_report(i, ctypes.byref(name), None, None) != SS_OK:
+            break
+        idx[name.value.decode()] = i
+        i += 1
+    mask = 0
+    for nm in names:
+        mask |= 1 << idx[nm]
+    check(lib().ss_profile_kinds(mask))
 
 
 def profile_collect():

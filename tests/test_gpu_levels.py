@@ -1,0 +1,76 @@
+"""GPU: split-level recursion (buckets beyond one work-group's sort are
+sample-sorted again) and the per-level counts the library reports."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1608_08648_amd import api
+from paper_1608_08648_amd import native as N
+from paper_1608_08648_amd import workloads
+from tests.gpu_util import note, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_levels(levels, n, p_eff):
+    assert levels, "no split level reported"
+    assert levels[0]["segments"] == 1 and levels[0]["keys"] == n and levels[0]["buckets"] == p_eff
+    for up, lo in zip(levels, levels[1:]):
+        # only keys that a level did not sort in place can reach the next one
+        assert lo["keys"] <= up["keys"] - up["bucket_keys"]
+    assert sum(lv["bucket_keys"] for lv in levels) <= n
+
+
+@pytest.mark.parametrize("kind", ["keys", "pairs"])
+def test_oversize_buckets_go_one_level_down(kind):
+    """2^22 int32 keys with p = 256: the mean bucket (16384 keys) is at the
+    keys-only slot sort's capacity, so about half the buckets are split
+    again; the result stays bit-exact (stable for pairs)."""
+    n = 1 << 22
+    keys = workloads.keys_2p26(n, "uniform", workloads.seed_for(1, 0), np.int32)
+    perm = oracle.stable_perm(keys)
+    kd = torch.from_numpy(keys).cuda()
+    prm = api.params(p=256, s=16, seed=21)
+    vt = N.SS_V_NONE if kind == "keys" else N.SS_V_IOTA32
+    ws = api._workspace(api.workspace_size(n, N.SS_I32, vt, prm), kd.device)
+    note(f"levels {kind} 2^22 p=256")
+    if kind == "keys":
+        out = api.sort_keys(kd, prm, ws=ws)
+        np.testing.assert_array_equal(out.cpu().numpy(), keys[perm])
+    else:
+        ko, vo = api.sort_pairs(kd, iota="int32", prm=prm, ws=ws)
+        np.testing.assert_array_equal(ko.cpu().numpy(), keys[perm])
+        np.testing.assert_array_equal(vo.cpu().numpy(), perm.astype(np.int32))
+    levels = api.level_stats(ws)
+    _check_levels(levels, n, 256)
+    if kind == "keys":
+        assert len(levels) >= 2 and levels[1]["keys"] > 0
+    assert api.status(ws) == ""
+
+
+def test_level_counts_without_recursion_flag():
+    """SS_F_NO_RECURSION keeps every bucket at level 0 (oversize buckets are
+    sorted by the in-work-group fallbacks): one level, output still exact."""
+    n = 1 << 20
+    keys = workloads.uniform_u32(n, workloads.seed_for(0))
+    kd, kt = to_dev(keys)
+    prm = api.params(p=32, s=8, seed=3, flags=N.SS_F_NO_RECURSION)
+    ws = api._workspace(api.workspace_size(n, N.SS_U32, N.SS_V_NONE, prm), kd.device)
+    note("no recursion 2^20 p=32")
+    out = api.sort_keys(kd, prm, ws=ws, key_type=kt)
+    np.testing.assert_array_equal(to_host(out, np.uint32), np.sort(keys))
+    levels = api.level_stats(ws)
+    _check_levels(levels, n, 32)
+    assert len(levels) == 1
+
+
+def test_small_input_reports_no_level():
+    """An input that one work-group sorts directly runs no split level."""
+    keys = workloads.uniform_u32(1000, 5)
+    kd, kt = to_dev(keys)
+    prm = api.params(p=64, s=8)
+    ws = api._workspace(api.workspace_size(1000, N.SS_U32, N.SS_V_NONE, prm), kd.device)
+    out = api.sort_keys(kd, prm, ws=ws, key_type=kt)
+    np.testing.assert_array_equal(to_host(out, np.uint32), np.sort(keys))
+    assert api.level_stats(ws) == []
