@@ -193,7 +193,11 @@ def bench_sort(args):
     split_keys = sum(lv["keys"] for lv in levels)
     inplace = sum(lv["bucket_keys"] for lv in levels)
     bytes_per_step = {"classify": kb * split_keys, "scatter": 2 * kb * split_keys,
-                      "bucket_sort": 2 * kb * inplace, "bucket_leftover": 2 * kb * (n - inplace)}
+                      "bucket_sort": 2 * kb * inplace, "bucket_leftover": 2 * kb * (n - inplace),
+                      # wide split (p >= 1024): each of its two passes reads and writes every key
+                      # (keys equal to a splitter's key stay put: counted as moved, an upper bound)
+                      "split_coarse": 2 * kb * split_keys, "split_fine": 2 * kb * split_keys}
+    bytes_per_step = {k: v for k, v in bytes_per_step.items() if table.get(k, (0, 0))[1]}   # kinds that ran
     dom, roof = roofline_of(rep, args.steps, bytes_per_step)
     if roof is not None:
         roof["traffic"] = measured_traffic(dom, args)

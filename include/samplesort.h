@@ -57,6 +57,9 @@ enum { SS_RANDOM = 0,   /* Alg. 2: p*s-1 keys drawn uniformly (with replacement)
 #define SS_F_NO_RECURSION   4u  /* plan no split level below the top one: a bucket too large for
                                    one work-group is then sorted by a one-work-group merge sort
                                    (slow; for tests of that path) */
+#define SS_F_NO_WIDE        8u  /* keys-only sorts of 4-byte keys with p >= 1024 move the keys in
+                                   two passes (64 coarse buckets, then p/64 fine ones); this flag
+                                   keeps the one-pass split instead (for comparisons) */
 
 /* return codes */
 enum { SS_OK = 0, SS_EINVAL = -1, SS_EWORKSPACE = -2, SS_EHIP = -3, SS_EDEVICE = -4 };

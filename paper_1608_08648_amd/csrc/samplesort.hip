@@ -4,6 +4,7 @@
 // here allocates device memory or waits for the GPU (except ss_status).
 #include "../../include/samplesort.h"
 #include "ss_kernels.h"
+#include "ss_wide.h"
 
 #include <hip/hip_runtime.h>
 
@@ -43,11 +44,13 @@ int fail(int code, const char* fmt, ...) {
 // ---------------------------------------------------------------- profiling
 enum ProfKind {
   PK_INIT, PK_PLAN, PK_SAMPLE, PK_SAMPLE_SORT, PK_SAMPLE_MERGE, PK_TREE, PK_CLASSIFY, PK_SCAN, PK_SCATTER,
-  PK_BUCKET_SORT, PK_BUCKET_LEFT, PK_SMALL_SORT, PK_BLOCK_SORT_REGULAR, PK_GRAD, PK_COUNT
+  PK_BUCKET_SORT, PK_BUCKET_LEFT, PK_SMALL_SORT, PK_BLOCK_SORT_REGULAR, PK_GRAD, PK_SPLIT_COARSE, PK_SPLIT_FINE,
+  PK_COUNT
 };
 const char* const PROF_NAMES[PK_COUNT] = {
     "init", "plan", "sample", "sample_sort", "sample_merge", "tree", "classify", "scan", "scatter",
-    "bucket_sort", "bucket_leftover", "small_sort", "regular_blocks", "scatter_grad"};
+    "bucket_sort", "bucket_leftover", "small_sort", "regular_blocks", "scatter_grad", "split_coarse",
+    "split_fine"};
 
 struct Prof {
   bool on = false;
@@ -257,6 +260,10 @@ struct Plan {
   // regular sampling: sorted blocks and the nested segmented plan
   size_t o_regk = 0, o_regi = 0, o_regoff = 0, o_nested = 0;
   Plan* nested = nullptr;
+  // wide split (keys only, 4-byte keys, p >= 1024): count arrays and their scan partials
+  bool wide = false;
+  uint32_t wide_W = 0;
+  size_t o_whf = 0, o_whf_part = 0, o_wha = 0, o_wha_part = 0, o_wkeys = 0, o_wtags = 0, o_wcells = 0, o_whdr = 0;
   size_t bytes = 0;
   ~Plan() { delete nested; }
 };
@@ -325,7 +332,24 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   }
   P->o_tmp = L.take((size_t)ty.KW * n);
   P->o_vtmp = ty.VW ? L.take((size_t)ty.VW * n) : 0;
-  const bool recurse = !(prm.flags & SS_F_NO_RECURSION);
+  bool recurse = !(prm.flags & SS_F_NO_RECURSION);
+  // wide split: many buckets of keys only, each small enough for the round-based slot sort
+  P->wide = ty.VW == 0 && ty.KW == 4 && p >= 1024 && p <= (uint32_t)WIDE_PMAX && !(prm.flags & SS_F_NO_WIDE) &&
+            (double)n / p * spread(prm.s) < 65536.0;
+  if (P->wide) {
+    recurse = false;
+    const uint64_t W = cdiv(n, WIDE_TILE);
+    P->wide_W = (uint32_t)W;
+    const uint64_t nf = (uint64_t)p * (W + 2) + 1, na = (uint64_t)WIDE_P1 * W + 1;
+    P->o_whf = L.take(4 * nf);
+    P->o_whf_part = L.take(4 * (cdiv(nf, SCAN_BLOCK) + 1));
+    P->o_wha = L.take(4 * na);
+    P->o_wha_part = L.take(4 * (cdiv(na, SCAN_BLOCK) + 1));
+    P->o_wkeys = L.take(4 * (size_t)p);
+    P->o_wtags = L.take(4 * (size_t)p);
+    P->o_wcells = L.take(4 * (size_t)WIDE_CELLS);
+    P->o_whdr = L.take(sizeof(WideHdr));
+  }
   plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp);
   if (P->regular) {
     // blocks sorted with their in-block index as payload (Alg. 1 step 1)
@@ -460,6 +484,64 @@ uint32_t grid_of(uint64_t work, uint32_t per, uint32_t cap) {
   return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(g, 1), cap);
 }
 
+// The wide split of a single keys-only sort (level 0 after its splitter
+// tree): count, scans, two split passes, bucket sorts.  The keys travel
+// input -> stage -> fine -> output; with input == output the stage is the
+// workspace copy and the bucket sort works in place.
+int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, int exp, hipStream_t st) {
+  WideArgs w{};
+  const bool inplace = in == out;
+  uint32_t* tmp = (uint32_t*)(ws + P.o_tmp);
+  w.tree = (const uint64_t*)a.tree;
+  w.hf = (uint32_t*)(ws + P.o_whf);
+  w.ha = (uint32_t*)(ws + P.o_wha);
+  w.src = in;
+  w.stage = inplace ? tmp : (uint32_t*)out;
+  w.fine = inplace ? (uint32_t*)out : tmp;
+  w.out = out;
+  w.n = (uint32_t)P.n;
+  w.p = P.p_eff;
+  w.lgp = 31 - __builtin_clz(P.p_eff);
+  w.W = P.wide_W;
+  w.tile = WIDE_TILE;
+  w.skeys = (uint32_t*)(ws + P.o_wkeys);
+  w.stags = (uint32_t*)(ws + P.o_wtags);
+  w.cells = (uint32_t*)(ws + P.o_wcells);
+  w.hdr = (WideHdr*)(ws + P.o_whdr);
+  w.kin = P.ty.kind;
+  w.kout = P.ty.kind;
+  // the leftover kernel sorts fine -> out (the stage is free scratch by then)
+  a.dst = w.fine;
+  a.out = out;
+  a.tmp = w.stage;
+  const uint64_t nf = (uint64_t)w.p * (w.W + 2) + 1, na = (uint64_t)WIDE_P1 * w.W + 1;
+  uint32_t* pf = (uint32_t*)(ws + P.o_whf_part);
+  uint32_t* pa = (uint32_t*)(ws + P.o_wha_part);
+  LAUNCH(PK_INIT, k_wide_zero, dim3(grid_of(w.p, 256, 64)), dim3(256), 0, st, w);
+  LAUNCH(PK_TREE, k_wide_table, dim3(1), dim3(NT), 0, st, w);
+  LAUNCH(PK_CLASSIFY, k_wide_count, dim3(w.W), dim3(NT), 0, st, w);
+  LAUNCH_CHECK();
+  const uint32_t nbf = (uint32_t)cdiv(nf, SCAN_BLOCK), nba = (uint32_t)cdiv(na, SCAN_BLOCK);
+  LAUNCH(PK_SCAN, k_scan_reduce, dim3(nbf), dim3(NT), 0, st, (const uint32_t*)w.hf, pf, nf, (const uint64_t*)nullptr);
+  LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, pf, nf, (const uint64_t*)nullptr);
+  LAUNCH(PK_SCAN, k_scan_down, dim3(nbf), dim3(NT), 0, st, w.hf, (const uint32_t*)pf, nf, (const uint64_t*)nullptr);
+  LAUNCH(PK_SCAN, k_scan_reduce, dim3(nba), dim3(NT), 0, st, (const uint32_t*)w.ha, pa, na, (const uint64_t*)nullptr);
+  LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, pa, na, (const uint64_t*)nullptr);
+  LAUNCH(PK_SCAN, k_scan_down, dim3(nba), dim3(NT), 0, st, w.ha, (const uint32_t*)pa, na, (const uint64_t*)nullptr);
+  LAUNCH_CHECK();
+  LAUNCH(PK_SPLIT_COARSE, k_wide_split_a, dim3(w.W), dim3(NT), 0, st, w);
+  LAUNCH_CHECK();
+  // pieces of the second pass: at most one per WIDE_TB keys of each region, plus one per region
+  const uint32_t pieces = (uint32_t)(cdiv(P.n, WIDE_TB) + WIDE_P1);
+  LAUNCH(PK_SPLIT_FINE, k_wide_split_b, dim3(pieces), dim3(NT), 0, st, w);
+  LAUNCH_CHECK();
+  LAUNCH(PK_BUCKET_SORT, k_wide_bucket, dim3(w.p), dim3(WIDE_BNT), 0, st, a, w, exp);
+  LAUNCH_CHECK();
+  LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<4>), dim3(std::min<uint32_t>(w.p, 512)), dim3(NT), 0, st, a);
+  LAUNCH_CHECK();
+  return SS_OK;
+}
+
 template <int KW, int VW>
 int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st) {
   const uint32_t Cs = sample_cap(KW);
@@ -500,14 +582,24 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       LAUNCH(PK_SAMPLE_SORT, k_sample_sort_wg<KW>, dim3(lv.seg_cap), dim3(NT), 0, st, a, exp);
     }
     LAUNCH_CHECK();
+    if constexpr (KW == 4 && VW == 0) {
+      if (l == 0 && P.wide) {
+        int rc = run_wide(P, ws, a, in, out, exp, st);
+        if (rc) return rc;
+        continue;
+      }
+    }
     const uint32_t tiles = (uint32_t)lv.tiles_cap;
     if (lv.pmax > 256) LAUNCH(PK_CLASSIFY, (k_classify<KW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
     else LAUNCH(PK_CLASSIFY, (k_classify<KW, 256>), dim3(tiles), dim3(NT), 0, st, a);
     LAUNCH_CHECK();
     const uint32_t nb = (uint32_t)cdiv(std::max<uint64_t>(lv.hist_cap, 1), SCAN_BLOCK);
-    LAUNCH(PK_SCAN, k_scan_reduce, dim3(nb), dim3(NT), 0, st, a);
-    LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, a);
-    LAUNCH(PK_SCAN, k_scan_down, dim3(nb), dim3(NT), 0, st, a);
+    const uint64_t* tot_dev = &a.ctl->total_hist;
+    LAUNCH(PK_SCAN, k_scan_reduce, dim3(nb), dim3(NT), 0, st, (const uint32_t*)a.hist, a.scan_part, (uint64_t)0,
+           tot_dev);
+    LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, a.scan_part, (uint64_t)0, tot_dev);
+    LAUNCH(PK_SCAN, k_scan_down, dim3(nb), dim3(NT), 0, st, a.hist, (const uint32_t*)a.scan_part, (uint64_t)0,
+           tot_dev);
     LAUNCH_CHECK();
     if constexpr (VW == 0) {
       // keys only: equal keys are bit-identical, so placement order inside a bucket is free

@@ -761,41 +761,48 @@ __global__ void __launch_bounds__(NT) k_classify(LevelArgs a) {
   for (uint32_t b = threadIdx.x; b < d.p; b += NT) a.hist[d.hist_off + (uint64_t)b * d.ntiles + tw] = cnt[b];
 }
 
-// Exclusive scan of the level's counts (u32, wrapping mod 2^32; only
-// differences inside one segment are used, and those are < 2^32).
-__global__ void __launch_bounds__(NT) k_scan_reduce(LevelArgs a) {
+// Exclusive scan of an array of counts in place (u32, wrapping mod 2^32;
+// only differences inside one sort problem are used, and those are < 2^32).
+// The length is total_dev[0] when total_dev is given, else total.
+__device__ __forceinline__ uint64_t scan_len(uint64_t total, const uint64_t* total_dev) {
+  return total_dev ? *total_dev : total;
+}
+
+__global__ void __launch_bounds__(NT) k_scan_reduce(const uint32_t* h, uint32_t* part, uint64_t total_h,
+                                                    const uint64_t* total_dev) {
   __shared__ uint32_t sh[NT / WAVE + 2];
-  const uint64_t total = a.ctl->total_hist;
+  const uint64_t total = scan_len(total_h, total_dev);
   uint64_t b0 = (uint64_t)blockIdx.x * SCAN_BLOCK;
   if (b0 >= total) return;
   uint32_t s = 0;
   for (int r = 0; r < SCAN_ITEMS; r++) {
     uint64_t i = b0 + (uint64_t)r * NT + threadIdx.x;
-    if (i < total) s += a.hist[i];
+    if (i < total) s += h[i];
   }
   uint32_t tot;
   block_excl_scan<NT>(s, sh, &tot);
-  if (threadIdx.x == 0) a.scan_part[blockIdx.x] = tot;
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(NT) k_scan_partials(LevelArgs a) {
+__global__ void __launch_bounds__(NT) k_scan_partials(uint32_t* part, uint64_t total_h, const uint64_t* total_dev) {
   __shared__ uint32_t sh[NT / WAVE + 2];
-  const uint64_t total = a.ctl->total_hist;
+  const uint64_t total = scan_len(total_h, total_dev);
   const uint32_t nb = (uint32_t)((total + SCAN_BLOCK - 1) / SCAN_BLOCK);
   uint32_t run = 0;
   for (uint32_t base = 0; base < nb; base += NT) {
     uint32_t i = base + threadIdx.x;
-    uint32_t v = i < nb ? a.scan_part[i] : 0;
+    uint32_t v = i < nb ? part[i] : 0;
     uint32_t tot;
     uint32_t e = block_excl_scan<NT>(v, sh, &tot);
-    if (i < nb) a.scan_part[i] = run + e;
+    if (i < nb) part[i] = run + e;
     run += tot;
   }
 }
 
-__global__ void __launch_bounds__(NT) k_scan_down(LevelArgs a) {
+__global__ void __launch_bounds__(NT) k_scan_down(uint32_t* h, const uint32_t* part, uint64_t total_h,
+                                                  const uint64_t* total_dev) {
   __shared__ uint32_t sh[NT / WAVE + 2];
-  const uint64_t total = a.ctl->total_hist;
+  const uint64_t total = scan_len(total_h, total_dev);
   uint64_t b0 = (uint64_t)blockIdx.x * SCAN_BLOCK;
   if (b0 >= total) return;
   // thread t owns the SCAN_ITEMS consecutive entries starting at b0 + t*SCAN_ITEMS
@@ -803,14 +810,14 @@ __global__ void __launch_bounds__(NT) k_scan_down(LevelArgs a) {
   uint32_t s = 0;
   for (int k = 0; k < SCAN_ITEMS; k++) {
     uint64_t i = b0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
-    v[k] = i < total ? a.hist[i] : 0;
+    v[k] = i < total ? h[i] : 0;
     s += v[k];
   }
   uint32_t tot;
-  uint32_t run = block_excl_scan<NT>(s, sh, &tot) + a.scan_part[blockIdx.x];
+  uint32_t run = block_excl_scan<NT>(s, sh, &tot) + part[blockIdx.x];
   for (int k = 0; k < SCAN_ITEMS; k++) {
     uint64_t i = b0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
-    if (i < total) a.hist[i] = run;
+    if (i < total) h[i] = run;
     run += v[k];
   }
 }
@@ -1116,23 +1123,26 @@ template <int KW> struct SlotCap { static constexpr int C = KW == 4 ? 16128 : 80
 constexpr int SLOT_LOG2 = 13;                   // S = 8192 slots
 constexpr uint32_t SLOT_MAX_FILL = 48;          // crowded-slot limit
 
-template <int KW>
-struct SlotLds {
+template <int KW, int CAP>
+struct SlotLdsT {
   using KT = typename KeyOf<KW>::T;
-  static constexpr int C = SlotCap<KW>::C;
+  static constexpr int C = CAP;
   KT placed[C];
   uint32_t scnt[(1 << SLOT_LOG2) / 2];          // two 16-bit slot counters per word
   alignas(8) uint64_t red[64];
   uint32_t flag;
 };
+template <int KW>
+using SlotLds = SlotLdsT<KW, SlotCap<KW>::C>;
 
 //
 // lo_known / hi_known: a bound on the bucket's keys is already known (from
 // its splitters: keys of bucket b lie between splitter b's key and splitter
 // b+1's key); otherwise it is found with one pass over the bucket.
-template <int KW>
+// NTH threads per work-group, at most CAP keys.
+template <int KW, int NTH, int CAP>
 __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, typename KeyOf<KW>::T* out, uint64_t beg,
-                                          uint32_t len, int kin, int kout, SlotLds<KW>& sm,
+                                          uint32_t len, int kin, int kout, SlotLdsT<KW, CAP>& sm,
                                           bool lo_known = false, typename KeyOf<KW>::T lo = 0, bool hi_known = false,
                                           typename KeyOf<KW>::T hi = 0) {
   using KT = typename KeyOf<KW>::T;
@@ -1142,39 +1152,39 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
   const KT* in = src + beg;
   KT mn = ~KT(0), mx = 0;
   if (!(lo_known && hi_known))
-  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NT) {
+  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
     KT k[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) {
-      uint32_t i = i0 + u * NT + t;
+      uint32_t i = i0 + u * NTH + t;
       k[u] = i < len ? to_ord(in[i], kin) : KT(0);
     }
 #pragma unroll
     for (int u = 0; u < 8; u++)
-      if (i0 + u * NT + t < len) { mn = k[u] < mn ? k[u] : mn; mx = k[u] > mx ? k[u] : mx; }
+      if (i0 + u * NTH + t < len) { mn = k[u] < mn ? k[u] : mn; mx = k[u] > mx ? k[u] : mx; }
   }
-  for (int q = t; q < W; q += NT) sm.scnt[q] = 0;
-  if (!(lo_known && hi_known)) block_minmax<NT>(mn, mx, (KT*)sm.red);   // (ends with a barrier)
+  for (int q = t; q < W; q += NTH) sm.scnt[q] = 0;
+  if (!(lo_known && hi_known)) block_minmax<NTH>(mn, mx, (KT*)sm.red);   // (ends with a barrier)
   else __syncthreads();
   if (lo_known) mn = lo;
   if (hi_known) mx = hi;
   if (mn == mx) {                          // one key value: already sorted
-    for (uint32_t i = t; i < len; i += NT) out[beg + i] = from_ord(mn, kout);
+    for (uint32_t i = t; i < len; i += NTH) out[beg + i] = from_ord(mn, kout);
     return true;
   }
   const int bw = bit_width<KT>((KT)(mx - mn));
   const int sh = bw > SLOT_LOG2 ? bw - SLOT_LOG2 : 0;
   auto slot = [&](KT k) { return (uint32_t)((KT)(k - mn) >> sh); };
-  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NT) {
+  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
     KT k[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) {
-      uint32_t i = i0 + u * NT + t;
+      uint32_t i = i0 + u * NTH + t;
       k[u] = i < len ? to_ord(in[i], kin) : KT(0);
     }
 #pragma unroll
     for (int u = 0; u < 8; u++) {
-      if (i0 + u * NT + t < len) {
+      if (i0 + u * NTH + t < len) {
         uint32_t q = slot(k[u]);
         atomicAdd(&sm.scnt[q >> 1], 1u << (16 * (q & 1)));
       }
@@ -1183,7 +1193,7 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
   __syncthreads();
   // exclusive scan of the slot counts (16-bit halves), and the fullest slot
   {
-    constexpr int PER = W / NT;
+    constexpr int PER = W / NTH;
     uint32_t v[PER], sum = 0, mxc = 0;
 #pragma unroll
     for (int j = 0; j < PER; j++) {
@@ -1193,7 +1203,7 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
       mxc = max(mxc, max(lo, hi));
     }
     uint32_t tot;
-    uint32_t run = block_excl_scan<NT>(sum, (uint32_t*)sm.red, &tot);
+    uint32_t run = block_excl_scan<NTH>(sum, (uint32_t*)sm.red, &tot);
     uint32_t wm = wave_max(mxc);
     if (t == 0) sm.flag = 0;
     __syncthreads();
@@ -1212,16 +1222,16 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
   __syncthreads();
   if (crowded) return false;
   // place: afterwards each slot's counter holds the slot's end
-  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NT) {
+  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
     KT k[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) {
-      uint32_t i = i0 + u * NT + t;
+      uint32_t i = i0 + u * NTH + t;
       k[u] = i < len ? to_ord(in[i], kin) : KT(0);
     }
 #pragma unroll
     for (int u = 0; u < 8; u++) {
-      if (i0 + u * NT + t < len) {
+      if (i0 + u * NTH + t < len) {
         uint32_t q = slot(k[u]);
         uint32_t sft = 16 * (q & 1);
         uint32_t old = atomicAdd(&sm.scnt[q >> 1], 1u << sft);
@@ -1233,7 +1243,7 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
   // order each slot: a key's rank = keys of its slot that are smaller, or
   // equal and placed earlier
   auto slot_end = [&](uint32_t q) { return (sm.scnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu; };
-  for (uint32_t i = t; i < len; i += NT) {
+  for (uint32_t i = t; i < len; i += NTH) {
     KT k = sm.placed[i];
     uint32_t q = slot(k);
     uint32_t s0 = q ? slot_end(q - 1) : 0u, s1 = slot_end(q);
@@ -1278,7 +1288,7 @@ __global__ void __launch_bounds__(NT) k_bucket_sort_keys(LevelArgs a, int export
   const KT lo = lo_k ? spl_key(b) : KT(0);
   const KT hi = hi_k ? spl_key(b + 1) : KT(0);
   if (sz <= (uint32_t)SlotLds<KW>::C &&
-      slot_sort<KW>((const KT*)a.dst, (KT*)a.out, gb, sz, 0, a.kout, sm, lo_k, lo, hi_k, hi)) {
+      slot_sort<KW, NT, SlotCap<KW>::C>((const KT*)a.dst, (KT*)a.out, gb, sz, 0, a.kout, sm, lo_k, lo, hi_k, hi)) {
     if (threadIdx.x == 0) atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)sz);
     return;
   }

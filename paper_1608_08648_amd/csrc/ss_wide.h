@@ -1,0 +1,638 @@
+// Wide split: keys-only sort of 4-byte keys with many buckets (p >= 1024).
+//
+// One sample, its p-1 splitters and the (key, position) classification of
+// step 4 (ties between equal keys broken by the input position, Section
+// 2.2), exactly as in the level kernels.  What differs is how the keys move:
+// writing every tile straight into p buckets would leave runs of a few keys
+// per bucket, so the keys travel in two passes of long runs instead:
+//
+//   k_wide_table    sorted splitter keys and a cell table over their range
+//   k_wide_count    per tile: the fine bucket of every key (cell table and a
+//                   short binary search), non-tie counts per (bucket, tile),
+//                   tie counts per bucket
+//   k_scan_*        exclusive scans of both count arrays
+//   k_wide_split_a  per tile: non-tie keys to P1 = 64 coarse regions (a
+//                   coarse bucket is P2 = p / 64 consecutive fine buckets)
+//   k_wide_split_b  per piece of a coarse region: keys to their fine buckets
+//                   (walk of the region's own subtree on the key alone)
+//   k_wide_bucket   per fine bucket: fill the tie runs, sort the rest in LDS
+//
+// A tie key is a key equal to the key of one of its bucket's two splitters.
+// Every other key differs from all p-1 splitter keys (the splitters are
+// sorted, so any splitter key equal to it would bound its bucket), so for it
+// the comparison with a splitter is decided by the key alone and the second
+// pass needs no position.  Tie keys are never moved: a key equal to the
+// lower splitter's key is no larger than any other key of its bucket, one
+// equal to the upper splitter's key no smaller, so the bucket sort writes
+// them as runs of that key at the bucket's two ends.  Bucket contents, and
+// hence the output, are those of the one-pass split.
+//
+// Layout of the fine counts: bucket b owns R = W + 2 entries,
+//   [b*R]          keys equal to the lower splitter's key (tie-low)
+//   [b*R + 1 + w]  non-tie keys of input tile w
+//   [b*R + W + 1]  keys equal to the upper splitter's key (tie-high)
+// plus one last entry (0) so that, scanned, it holds n.  After the scan
+// every entry is a final output position: bucket b starts at [b*R], its
+// non-tie keys from tile w go to [b*R + 1 + w] onwards.
+#pragma once
+#include "ss_kernels.h"
+
+namespace ss {
+
+constexpr int WIDE_LG1 = 6;
+constexpr uint32_t WIDE_P1 = 1u << WIDE_LG1;   // coarse buckets
+constexpr int WIDE_PMAX = 4096;
+constexpr int WIDE_U = 16;                     // keys per thread per chunk
+constexpr int WIDE_CH = WIDE_U * NT;
+constexpr uint32_t WIDE_TILE = 7 * WIDE_U * 512; // keys per input tile (< 2^16: 16-bit tie counters)
+constexpr uint32_t WIDE_TB = 65536;            // nominal keys per piece of the second pass
+// bucket sort of the wide split: 1024 threads, 30720 keys per round in LDS
+// (one work-group per CU), buckets of up to 65535 keys
+constexpr int WIDE_BNT = 1024;
+constexpr int WIDE_BCAP = 30720;
+
+struct WideHdr { uint32_t kmin, kmax, sh, ncell; };
+
+struct WideArgs {
+  const uint64_t* tree;   // Eytzinger tree, slot k in [1, p): (ord << 32) | tag
+  uint32_t* hf;           // fine counts, p * (W + 2) + 1 entries, scanned in place
+  uint32_t* ha;           // coarse non-tie counts, P1 * W + 1 entries (c-major), scanned in place
+  const void* src;        // the caller's keys
+  uint32_t* stage;        // coarse regions (ord images)
+  uint32_t* fine;         // fine buckets (ord images)
+  void* out;              // output (caller's key type)
+  uint32_t* skeys;        // sorted splitter keys, rank 1..p-1 (entry 0 unused)
+  uint32_t* stags;        // their tags
+  uint32_t* cells;        // cell table
+  WideHdr* hdr;
+  uint32_t n, p, lgp, W, tile;
+  int kin, kout;
+};
+
+// Classification without a tree walk.  The sorted splitter keys are cut
+// into cells of equal key range: cell j of the range [kmin, kmax] of the
+// splitter keys covers keys kmin + [j << sh, (j + 1) << sh), and cells[j]
+// packs L_j | U_j << 16 with L_j = #{splitters whose key < the cell's first
+// key} and U_j = L_{j+1}.  A key in cell j has between L_j and U_j
+// splitters below it; a binary search over those few candidates (about p
+// / cells of them for evenly spread keys) finds the count.
+constexpr int WIDE_CELL_BITS = 11;
+constexpr int WIDE_CELLS = 1 << WIDE_CELL_BITS;
+
+// One work-group: the sorted splitters (rank r in [1, p): key and tag) from
+// the Eytzinger tree, and the cell table.
+__global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
+  __shared__ uint32_t sk[WIDE_PMAX];
+  const uint32_t p = w.p;
+  for (uint32_t r = threadIdx.x + 1; r < p; r += NT) {
+    const uint32_t z = __builtin_ctz(r);
+    const uint32_t k = (1u << (w.lgp - 1 - z)) + (r >> (z + 1));
+    const uint64_t nd = w.tree[k];
+    sk[r] = (uint32_t)(nd >> 32);
+    w.skeys[r] = (uint32_t)(nd >> 32);
+    w.stags[r] = (uint32_t)nd;
+  }
+  __syncthreads();
+  const uint32_t kmin = sk[1], kmax = sk[p - 1];
+  const int bw = bit_width<uint32_t>(kmax - kmin);
+  const uint32_t sh = bw > WIDE_CELL_BITS ? (uint32_t)(bw - WIDE_CELL_BITS) : 0u;
+  const uint32_t ncell = ((kmax - kmin) >> sh) + 1;
+  // L(j) = #{r : sk[r] < kmin + (j << sh)}, with 64-bit cell starts
+  auto L = [&](uint32_t j) -> uint32_t {
+    const uint64_t x = (uint64_t)kmin + ((uint64_t)j << sh);
+    uint32_t a = 1, z = p;                  // first r in [1, p) with sk[r] >= x, or p
+    while (a < z) {
+      uint32_t m = (a + z) / 2;
+      if ((uint64_t)sk[m] < x) a = m + 1;
+      else z = m;
+    }
+    return a - 1;
+  };
+  for (uint32_t j = threadIdx.x; j < ncell; j += NT) w.cells[j] = L(j) | (L(j + 1) << 16);
+  if (threadIdx.x == 0) *w.hdr = WideHdr{kmin, kmax, sh, ncell};
+}
+
+// Search of one key among the candidates of its cell, on the key alone.
+// lo - 1 = #{splitters whose key < key}; tie = some splitter has this key
+// (then it is splitter lo: the first with key >= key is always compared).
+__device__ __forceinline__ uint32_t wide_lower(const uint32_t* sk, const uint32_t* cells, const WideHdr& h,
+                                               uint32_t p, uint32_t key, bool& tie) {
+  tie = false;
+  if (key < h.kmin) return 1;
+  if (key > h.kmax) return p;
+  const uint32_t cell = cells[(key - h.kmin) >> h.sh];
+  uint32_t lo = (cell & 0xFFFFu) + 1, len = (cell >> 16) - (cell & 0xFFFFu);
+  uint32_t hk = ~key;
+  while (len) {
+    const uint32_t half = len >> 1, m = lo + half, v = sk[m];
+    if (v < key) {
+      lo = m + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+      hk = v;
+    }
+  }
+  tie = hk == key;
+  return lo;
+}
+
+// Full classification of step 4 for a tie key (splitter lo has its key):
+// b = (lo - 1) + #{r >= lo : (sk[r], st[r]) < (key, tag)}; tie-low when
+// splitter b has the key, else tie-high (splitter b + 1 = lo has it).
+__device__ __forceinline__ uint32_t wide_tie_bucket(const uint32_t* sk, const uint32_t* st, uint32_t p, uint32_t lo,
+                                                    uint32_t key, uint32_t tag, uint32_t& kind) {
+  uint32_t a = lo, z = p;                   // first r in [lo, p) with (sk, st)[r] >= (key, tag)
+  while (a < z) {
+    const uint32_t m = (a + z) / 2;
+    if (sk[m] == key && st[m] < tag) a = m + 1;
+    else z = m;
+  }
+  kind = a > lo ? 1u : 2u;
+  return a - 1;
+}
+
+// Tie entries and the trailing total of both count arrays start at zero
+// (the count kernel adds to them; it writes every other entry).
+__global__ void __launch_bounds__(256) k_wide_zero(WideArgs w) {
+  const uint32_t R = w.W + 2;
+  for (uint32_t b = blockIdx.x * 256 + threadIdx.x; b < w.p; b += gridDim.x * 256) {
+    w.hf[(uint64_t)b * R] = 0;
+    w.hf[(uint64_t)b * R + R - 1] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    w.hf[(uint64_t)w.p * R] = 0;
+    w.ha[(uint64_t)WIDE_P1 * w.W] = 0;
+  }
+}
+
+// keys of one chunk, issued ahead of their use (prefetch into registers)
+__device__ __forceinline__ void wide_load(uint32_t (&k)[WIDE_U], const uint32_t* src, uint32_t i0, uint32_t end) {
+  const int t = threadIdx.x;
+  if (i0 + WIDE_CH <= end) {
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) k[u] = src[i0 + u * NT + t];
+  } else {
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) {
+      const uint32_t i = i0 + u * NT + t;
+      k[u] = i < end ? src[i] : 0u;
+    }
+  }
+}
+
+struct WideCountLds {
+  uint32_t sk[WIDE_PMAX];        // sorted splitter keys (rank 1..p-1)
+  uint32_t st[WIDE_PMAX];        // their tags
+  uint32_t cells[WIDE_CELLS];
+  uint32_t cnt[WIDE_PMAX];       // non-tie keys per fine bucket
+  uint32_t ties[WIDE_PMAX];      // tie-low | tie-high << 16 (a tile holds < 2^16 keys)
+  uint32_t csum[WIDE_P1];
+  WideHdr h;
+};
+
+// Per tile: classify every key (step 4) and count.  Runs of equal (kind,
+// bucket) in a thread's keys are added to the LDS counters at once.
+__global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
+  __shared__ WideCountLds sm;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= w.W) return;
+  const int t = threadIdx.x;
+  const uint32_t p = w.p;
+  const uint32_t t0 = tile * w.tile, t1 = min(t0 + w.tile, w.n);
+  const uint32_t* src = (const uint32_t*)w.src;
+  uint32_t nk[WIDE_U];
+  wide_load(nk, src, t0, t1);
+  for (uint32_t k = t; k < p; k += NT) {
+    sm.sk[k] = w.skeys[k];
+    sm.st[k] = w.stags[k];
+    sm.cnt[k] = 0;
+    sm.ties[k] = 0;
+  }
+  const WideHdr h = *w.hdr;
+  for (uint32_t j = t; j < h.ncell; j += NT) sm.cells[j] = w.cells[j];
+  if (t < (int)WIDE_P1) sm.csum[t] = 0;
+  __syncthreads();
+  uint32_t cur = ~0u, run = 0;       // run of equal (kind << 16 | bucket)
+  auto flush = [&]() {
+    if (!run) return;
+    const uint32_t kind = cur >> 16, b = cur & 0xFFFFu;
+    if (kind == 0) atomicAdd(&sm.cnt[b], run);
+    else atomicAdd(&sm.ties[b], kind == 1 ? run : run << 16);
+  };
+  for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_CH) {
+    uint32_t key[WIDE_U];
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) key[u] = to_ord(nk[u], w.kin);
+    if (i0 + WIDE_CH < t1) wide_load(nk, src, i0 + WIDE_CH, t1);
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) {
+      const uint32_t i = i0 + u * NT + t;
+      if (i < t1) {
+        bool tie;
+        const uint32_t lo = wide_lower(sm.sk, sm.cells, h, p, key[u], tie);
+        uint32_t b = lo - 1, kind = 0;
+        if (tie) b = wide_tie_bucket(sm.sk, sm.st, p, lo, key[u], i, kind);
+        const uint32_t idx = (kind << 16) | b;
+        if (idx != cur) {
+          flush();
+          cur = idx;
+          run = 0;
+        }
+        run++;
+      }
+    }
+  }
+  flush();
+  __syncthreads();
+  const uint32_t R = w.W + 2;
+  for (uint32_t b = t; b < p; b += NT) {
+    w.hf[(uint64_t)b * R + 1 + tile] = sm.cnt[b];
+    const uint32_t tl = sm.ties[b] & 0xFFFFu, th = sm.ties[b] >> 16;
+    if (tl) atomicAdd(&w.hf[(uint64_t)b * R], tl);
+    if (th) atomicAdd(&w.hf[(uint64_t)b * R + R - 1], th);
+  }
+  // non-tie keys per coarse bucket: each thread sums p / NT consecutive fine
+  // counts (all inside one coarse bucket, as p / NT <= p / P1)
+  {
+    const uint32_t K = p / NT, P2 = p >> WIDE_LG1;
+    uint32_t s = 0;
+    for (uint32_t j = 0; j < K; j++) s += sm.cnt[t * K + j];
+    if (s) atomicAdd(&sm.csum[(t * K) / P2], s);
+  }
+  __syncthreads();
+  if (t < (int)WIDE_P1) w.ha[(uint64_t)t * w.W + tile] = sm.csum[t];
+}
+
+// Grouping of one chunk by bucket in LDS, then contiguous run writes:
+// shared by both passes (NB buckets; bucket ~0u = key not moved).
+template <int NB>
+struct WideSplitLds {
+  uint32_t gofs[NB];       // output position of each bucket's run for the current chunk
+  uint32_t cur[2][NB];     // chunk counts, then cursors (alternating chunks)
+  uint32_t cst[2][NB];     // chunk start of each bucket (alternating chunks)
+  uint32_t ctot[2];        // keys of the chunk that move
+  uint32_t sk[WIDE_CH];
+  uint8_t sb[WIDE_CH];
+};
+
+template <int NB>
+__device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uint32_t (&key)[WIDE_U],
+                                                 const uint32_t (&bk)[WIDE_U], uint32_t* dst, int x, bool first) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < WIDE_U; u++)
+    if (bk[u] != ~0u) atomicAdd(&sm.cur[x][bk[u]], 1u);
+  __syncthreads();
+  // close the previous chunk's bookkeeping, then chunk starts of this one
+  // (NB <= 64: one wave)
+  if (t < NB) {
+    const int o = x ^ 1;
+    if (!first) {
+      sm.gofs[t] += sm.cur[o][t] - sm.cst[o][t];
+      sm.cur[o][t] = 0;
+    }
+    const uint32_t v = sm.cur[x][t];
+    const uint32_t inc = wave_incl_scan(v);
+    sm.cst[x][t] = inc - v;
+    sm.cur[x][t] = inc - v;
+    if (t == NB - 1) sm.ctot[x] = inc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < WIDE_U; u++) {
+    if (bk[u] != ~0u) {
+      const uint32_t pos = atomicAdd(&sm.cur[x][bk[u]], 1u);
+      sm.sk[pos] = key[u];
+      sm.sb[pos] = (uint8_t)bk[u];
+    }
+  }
+  __syncthreads();
+  const uint32_t tot = sm.ctot[x];
+#pragma unroll 4
+  for (uint32_t j = t; j < tot; j += NT) {
+    const uint32_t bb = sm.sb[j];
+    dst[sm.gofs[bb] + (j - sm.cst[x][bb])] = sm.sk[j];
+  }
+}
+
+struct WideALds {
+  uint32_t sk[WIDE_PMAX];
+  uint32_t cells[WIDE_CELLS];
+  WideSplitLds<WIDE_P1> g;
+};
+
+// First pass, per input tile: non-tie keys to their coarse region, in runs.
+// (For a non-tie key the count of splitters below it is decided by the key
+// alone; tie keys stay where they are.)
+__global__ void __launch_bounds__(NT) k_wide_split_a(WideArgs w) {
+  __shared__ WideALds sm;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= w.W) return;
+  const int t = threadIdx.x;
+  const uint32_t p = w.p, lg2 = w.lgp - WIDE_LG1;
+  const uint32_t t0 = tile * w.tile, t1 = min(t0 + w.tile, w.n);
+  const uint32_t* src = (const uint32_t*)w.src;
+  uint32_t nk[WIDE_U];
+  wide_load(nk, src, t0, t1);
+  for (uint32_t k = t; k < p; k += NT) sm.sk[k] = w.skeys[k];
+  const WideHdr h = *w.hdr;
+  for (uint32_t j = t; j < h.ncell; j += NT) sm.cells[j] = w.cells[j];
+  if (t < (int)WIDE_P1) {
+    sm.g.gofs[t] = w.ha[(uint64_t)t * w.W + tile];
+    sm.g.cur[0][t] = 0;
+    sm.g.cur[1][t] = 0;
+  }
+  __syncthreads();
+  int x = 0;
+  for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_CH, x ^= 1) {
+    uint32_t key[WIDE_U], c[WIDE_U];
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) key[u] = to_ord(nk[u], w.kin);
+    if (i0 + WIDE_CH < t1) wide_load(nk, src, i0 + WIDE_CH, t1);
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) {
+      bool tie;
+      const uint32_t lo = wide_lower(sm.sk, sm.cells, h, p, key[u], tie);
+      c[u] = (i0 + u * NT + t < t1 && !tie) ? ((lo - 1) >> lg2) : ~0u;
+    }
+    wide_group_write<WIDE_P1>(sm.g, key, c, w.stage, x, i0 == t0);
+  }
+}
+
+struct WideBLds {
+  uint32_t sub[64];        // the coarse bucket's subtree (keys), local Eytzinger slots [1, P2)
+  uint32_t info[4];
+  WideSplitLds<64> g;
+};
+
+// Second pass.  Coarse region c is cut into pieces at input-tile
+// boundaries: piece j holds the runs of the input tiles whose run starts in
+// [j*TB, (j+1)*TB) of the region, so its keys of fine bucket b go to the
+// scanned position of (b, first tile of the piece) onwards.
+__global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
+  __shared__ WideBLds sm;
+  const int t = threadIdx.x;
+  const uint32_t W = w.W, lg2 = w.lgp - WIDE_LG1, P2 = 1u << lg2;
+  if (t < WAVE) {
+    // which region and piece: lane c counts the pieces of region c
+    const uint32_t c = t;
+    uint32_t pieces = 0, rb = 0, re = 0;
+    if (c < WIDE_P1) {
+      rb = w.ha[(uint64_t)c * W];
+      re = w.ha[(uint64_t)(c + 1) * W];          // c = P1-1: the trailing total
+      pieces = (re - rb + WIDE_TB - 1) / WIDE_TB;
+    }
+    const uint32_t inc = wave_incl_scan(pieces);
+    const uint32_t bid = blockIdx.x;
+    const bool mine = c < WIDE_P1 && bid >= inc - pieces && bid < inc;
+    const uint64_t m = __ballot(mine);
+    if (t == 0) sm.info[0] = m ? (uint32_t)__builtin_ctzll(m) : ~0u;
+    if (mine) {
+      sm.info[1] = bid - (inc - pieces);
+      sm.info[2] = rb;
+      sm.info[3] = re;
+    }
+  }
+  __syncthreads();
+  const uint32_t c = sm.info[0];
+  if (c == ~0u) return;
+  const uint32_t j = sm.info[1], rb = sm.info[2], re = sm.info[3];
+  // input tiles whose run starts inside the piece: [wl, wh)
+  auto first_at = [&](uint32_t lim) {             // first w with run start - rb >= lim
+    uint32_t a = 0, z = W;
+    while (a < z) {
+      uint32_t mid = (a + z) / 2;
+      if (w.ha[(uint64_t)c * W + mid] - rb < lim) a = mid + 1;
+      else z = mid;
+    }
+    return a;
+  };
+  const uint32_t wl = first_at(j * WIDE_TB);
+  const uint32_t wh = first_at((j + 1) * WIDE_TB);
+  if (wl >= wh) return;                           // no run starts here (uniform across the group)
+  const uint32_t r0 = w.ha[(uint64_t)c * W + wl];
+  const uint32_t r1 = (wh < W) ? w.ha[(uint64_t)c * W + wh] : re;
+  uint32_t nk[WIDE_U];
+  wide_load(nk, w.stage, r0, r1);
+  const uint32_t R = W + 2;
+  if (t < 64) {                                   // P2 <= 64 fine buckets; the rest stay empty
+    const uint32_t l = t;
+    if (l > 0 && l < P2) {
+      const uint32_t d = 31 - __clz(l);
+      const uint32_t k = ((WIDE_P1 + c) << d) + (l - (1u << d));
+      sm.sub[l] = (uint32_t)(w.tree[k] >> 32);
+    }
+    sm.g.gofs[l] = l < P2 ? w.hf[(uint64_t)(c * P2 + l) * R + 1 + wl] : 0u;
+    sm.g.cur[0][l] = 0;
+    sm.g.cur[1][l] = 0;
+  }
+  __syncthreads();
+  int x = 0;
+  for (uint32_t i0 = r0; i0 < r1; i0 += WIDE_CH, x ^= 1) {
+    uint32_t key[WIDE_U], f[WIDE_U];
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) {
+      key[u] = nk[u];
+      f[u] = 1;
+    }
+    if (i0 + WIDE_CH < r1) wide_load(nk, w.stage, i0 + WIDE_CH, r1);
+    for (uint32_t l = 0; l < lg2; l++) {
+#pragma unroll
+      for (int u = 0; u < WIDE_U; u++) f[u] = 2 * f[u] + (sm.sub[f[u]] < key[u] ? 1u : 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) f[u] = (i0 + u * NT + t < r1) ? f[u] - P2 : ~0u;
+    wide_group_write<64>(sm.g, key, f, w.fine, x, i0 == r0);
+  }
+}
+
+// Slot sort of up to 65535 keys in rounds (4-byte ord keys).  As the slot
+// sort of the level kernels: slot(key) = (key - lo) >> sh over S = 8192
+// slots, count, scan, place, then order each slot's few keys.  A bucket
+// larger than the LDS is handled in rounds: round r places the keys of the
+// slots whose start lies in [r*C', (r+1)*C'), C' = CAP - SLOT_MAX_FILL, so a
+// round never holds more than CAP keys.  Each round re-reads the bucket
+// (from L2).  Returns false (having written nothing) when a slot is too
+// crowded or the bucket too large.
+template <int CAP>
+struct SlotRoundsLds {
+  uint32_t placed[CAP];
+  uint32_t cnt[1 << SLOT_LOG2];   // counts, then slot starts, then slot cursors / ends
+  alignas(8) uint64_t red[64];
+  uint32_t flag;
+  uint32_t rslot[8], rbase[8];    // first slot and first position of each round
+};
+
+template <int NTH, int CAP>
+__device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* out, uint32_t len, int kout,
+                                                 SlotRoundsLds<CAP>& sm, bool lo_known, uint32_t lo, bool hi_known,
+                                                 uint32_t hi) {
+  constexpr int S = 1 << SLOT_LOG2;
+  constexpr uint32_t CR = CAP - SLOT_MAX_FILL;
+  const int t = threadIdx.x;
+  if (len > 65535u) return false;
+  uint32_t mn = ~0u, mx = 0;
+  if (!(lo_known && hi_known)) {
+    for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
+      uint32_t k[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        uint32_t i = i0 + u * NTH + t;
+        k[u] = i < len ? in[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u++)
+        if (i0 + u * NTH + t < len) { mn = k[u] < mn ? k[u] : mn; mx = k[u] > mx ? k[u] : mx; }
+    }
+  }
+  for (int q = t; q < S; q += NTH) sm.cnt[q] = 0;
+  if (!(lo_known && hi_known)) block_minmax<NTH>(mn, mx, (uint32_t*)sm.red);   // (ends with a barrier)
+  else __syncthreads();
+  if (lo_known) mn = lo;
+  if (hi_known) mx = hi;
+  if (mn == mx) {                          // one key value: already sorted
+    for (uint32_t i = t; i < len; i += NTH) out[i] = from_ord(mn, kout);
+    return true;
+  }
+  const int bw = bit_width<uint32_t>(mx - mn);
+  const int sh = bw > SLOT_LOG2 ? bw - SLOT_LOG2 : 0;
+  auto slot = [&](uint32_t k) { return (k - mn) >> sh; };
+  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
+    uint32_t k[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      uint32_t i = i0 + u * NTH + t;
+      k[u] = i < len ? in[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+      if (i0 + u * NTH + t < len) atomicAdd(&sm.cnt[slot(k[u])], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the slot counts, and the fullest slot
+  {
+    constexpr int PER = S / NTH;
+    uint32_t v[PER], sum = 0, mxc = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      v[j] = sm.cnt[t * PER + j];
+      sum += v[j];
+      mxc = max(mxc, v[j]);
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<NTH>(sum, (uint32_t*)sm.red, &tot);
+    uint32_t wm = wave_max(mxc);
+    if (t == 0) sm.flag = 0;
+    __syncthreads();
+    if (lane_id() == 0 && wm > SLOT_MAX_FILL) atomicOr(&sm.flag, 1u);
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      sm.cnt[t * PER + j] = run;
+      run += v[j];
+    }
+  }
+  __syncthreads();
+  const bool crowded = sm.flag != 0;
+  __syncthreads();
+  if (crowded) return false;
+  // first slot whose start is >= x (slot starts are non-decreasing; S if none)
+  auto first_slot = [&](uint32_t x) {
+    uint32_t a = 0, z = S;
+    while (a < z) {
+      uint32_t m = (a + z) / 2;
+      if (sm.cnt[m] < x) a = m + 1;
+      else z = m;
+    }
+    return a;
+  };
+  // round boundaries, taken while cnt still holds the slot starts
+  // (len < 2^16 and CR > 2^14: at most four rounds)
+  const uint32_t rounds = (len + CR - 1) / CR;
+  if (t <= (int)rounds) {
+    const uint32_t b = (t == 0) ? 0u : ((uint32_t)t < rounds ? first_slot(t * CR) : (uint32_t)S);
+    sm.rslot[t] = b;
+    sm.rbase[t] = b < (uint32_t)S ? sm.cnt[b] : len;
+  }
+  __syncthreads();
+  for (uint32_t r = 0; r < rounds; r++) {
+    // slots [qa, qb) of this round; slots below qa already hold their ends
+    const uint32_t qa = sm.rslot[r], qb = sm.rslot[r + 1], base = sm.rbase[r];
+    for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
+      uint32_t k[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        uint32_t i = i0 + u * NTH + t;
+        k[u] = i < len ? in[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        if (i0 + u * NTH + t < len) {
+          const uint32_t q = slot(k[u]);
+          if (q >= qa && q < qb) sm.placed[atomicAdd(&sm.cnt[q], 1u) - base] = k[u];
+        }
+      }
+    }
+    __syncthreads();
+    // order each slot: a key's rank = keys of its slot that are smaller, or
+    // equal and placed earlier (cnt[q] is now the end of slot q for q < qb)
+    const uint32_t top = (qb < (uint32_t)S ? sm.cnt[qb - 1] : len) - base;
+    for (uint32_t i = t; i < top; i += NTH) {
+      const uint32_t k = sm.placed[i];
+      const uint32_t q = slot(k);
+      const uint32_t s0 = (q ? sm.cnt[q - 1] : 0u) - base, s1 = sm.cnt[q] - base;
+      uint32_t rank = 0;
+      for (uint32_t j = s0; j < s1; j++) {
+        const uint32_t o = sm.placed[j];
+        rank += (o < k || (o == k && j < i)) ? 1u : 0u;
+      }
+      out[base + s0 + rank] = from_ord(k, kout);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// One fine bucket per work-group: write its tie runs, slot-sort its other
+// keys (or hand them to the leftover list).
+__global__ void __launch_bounds__(WIDE_BNT) k_wide_bucket(LevelArgs a, WideArgs w, int export_stages) {
+  __shared__ SlotRoundsLds<WIDE_BCAP> sm;
+  const uint32_t b = blockIdx.x;
+  if (b >= w.p) return;
+  const int t = threadIdx.x;
+  const uint32_t R = w.W + 2;
+  const uint32_t beg = w.hf[(uint64_t)b * R], nt0 = w.hf[(uint64_t)b * R + 1];
+  const uint32_t nt1 = w.hf[(uint64_t)b * R + R - 1], end = w.hf[(uint64_t)(b + 1) * R];
+  if (export_stages && t == 0) a.exp_counts[b] = end - beg;
+  auto spl_key = [&](uint32_t r) -> uint32_t {   // key of splitter of rank r (1-based)
+    const uint32_t z = __builtin_ctz(r);
+    const uint32_t k = (1u << (w.lgp - 1 - z)) + (r >> (z + 1));
+    return (uint32_t)(w.tree[k] >> 32);
+  };
+  const bool lo_k = b >= 1, hi_k = b + 1 < w.p;
+  const uint32_t lo = lo_k ? spl_key(b) : 0u;
+  const uint32_t hi = hi_k ? spl_key(b + 1) : 0u;
+  uint32_t* out = (uint32_t*)w.out;
+  if (nt0 > beg) {
+    const uint32_t v = from_ord(lo, w.kout);
+    for (uint32_t i = beg + t; i < nt0; i += WIDE_BNT) out[i] = v;
+  }
+  if (end > nt1) {
+    const uint32_t v = from_ord(hi, w.kout);
+    for (uint32_t i = nt1 + t; i < end; i += WIDE_BNT) out[i] = v;
+  }
+  const uint32_t sz = nt1 - nt0;
+  bool done = sz == 0;
+  if (!done) done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP>(w.fine + nt0, out + nt0, sz, w.kout, sm, lo_k, lo, hi_k, hi);
+  if (t == 0) {
+    if (done) {
+      atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)(end - beg));
+    } else {
+      atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)(end - beg - sz));
+      const uint32_t k = atomicAdd(a.nleft, 1u);
+      a.left[k] = SmallEnt{nt0, sz, b};
+    }
+  }
+}
+
+}  // namespace ss
