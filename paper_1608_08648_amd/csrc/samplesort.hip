@@ -112,6 +112,7 @@ uint32_t small_cap(int KW, int VW) {
   return (uint32_t)NT * (s <= 4 ? 64 : (s <= 8 ? 32 : 16));
 }
 uint32_t sample_cap(int KW) { return (uint32_t)NT * (KW == 4 ? 32 : 16); }
+uint32_t sample_chunk(int KW) { return KW == 4 ? (uint32_t)SampleChunk<4>::C : (uint32_t)SampleChunk<8>::C; }
 // keys-only buckets up to this size are sorted by the slot sort
 uint32_t slot_cap(int KW) { return KW == 4 ? (uint32_t)SlotCap<4>::C : (uint32_t)SlotCap<8>::C; }
 uint32_t split_chunk(int KW, int VW) { return (uint32_t)NT * ((KW + VW <= 4) ? 8 : 4); }
@@ -160,7 +161,7 @@ uint32_t default_tile(uint32_t p) {
 struct LevelPlan {
   uint32_t tile = 0, seg_cap = 0, pmax = 256, p_cap = 256, target = 0, s = 1;
   uint64_t samp_cap = 0, tiles_cap = 0, hist_cap = 0, bkt_cap = 0;
-  size_t o_segs = 0, o_sord = 0, o_stag = 0, o_tree = 0, o_ttag = 0, o_hist = 0, o_part = 0, o_left = 0;
+  size_t o_segs = 0, o_sord = 0, o_stag = 0, o_tree = 0, o_ttag = 0, o_hist = 0, o_part = 0, o_left = 0, o_left2 = 0;
 };
 
 struct LevelsPlan {
@@ -225,10 +226,12 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
     lv.o_hist = L.take(4 * std::max<uint64_t>(lv.hist_cap, 1));
     lv.o_part = L.take(4 * (cdiv(std::max<uint64_t>(lv.hist_cap, 1), SCAN_BLOCK) + 1));
     lv.o_left = L.take(sizeof(SmallEnt) * std::max<uint64_t>(lv.bkt_cap, 1));
+    lv.o_left2 = L.take(sizeof(SmallEnt) * std::max<uint64_t>(lv.bkt_cap, 1));
     if (l == 0 && p0 && m0 > Cs) {
       P->big_sample = true;
       P->merge_passes = 0;
-      while (((uint64_t)Cs << P->merge_passes) < m0) P->merge_passes++;
+      const uint64_t ch = sample_chunk(ty.KW);
+      while ((ch << P->merge_passes) < m0) P->merge_passes++;
       P->o_sord2 = L.take((size_t)ty.KW * m0);
       P->o_stag2 = L.take(4 * m0);
     }
@@ -462,6 +465,8 @@ LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void*
   a.scan_part = (uint32_t*)(ws + lv.o_part);
   a.left = (SmallEnt*)(ws + lv.o_left);
   a.nleft = &g->nleft[l];
+  a.left2 = (SmallEnt*)(ws + lv.o_left2);
+  a.nleft2 = &g->nleft2[l];
   if (P.exp && l == 0) {
     a.exp_smp_ord = (uint64_t*)(ws + P.o_exp_so);
     a.exp_smp_tag = (uint64_t*)(ws + P.o_exp_st);
@@ -537,7 +542,7 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   LAUNCH_CHECK();
   LAUNCH(PK_BUCKET_SORT, k_wide_bucket, dim3(w.p), dim3(WIDE_BNT), 0, st, a, w, exp);
   LAUNCH_CHECK();
-  LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<4>), dim3(std::min<uint32_t>(w.p, 512)), dim3(NT), 0, st, a);
+  LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<4>), dim3(std::min<uint32_t>(w.p, 512)), dim3(NT), 0, st, a, 0);
   LAUNCH_CHECK();
   return SS_OK;
 }
@@ -562,14 +567,15 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
     LAUNCH_CHECK();
     // sample sort and splitter tree
     if (l == 0 && P.lp.big_sample) {
-      LAUNCH(PK_SAMPLE_SORT, k_sample_chunk_sort<KW>, dim3((uint32_t)cdiv(P.m, Cs)), dim3(NT), 0, st, a);
+      const uint32_t ch = sample_chunk(KW);
+      LAUNCH(PK_SAMPLE_SORT, k_sample_chunk_sort<KW>, dim3((uint32_t)cdiv(P.m, ch)), dim3(NT), 0, st, a);
       LAUNCH_CHECK();
       void* so = a.s_ord;
       uint32_t* stg = a.s_tag;
       void* so2 = a.s_ord2;
       uint32_t* st2 = a.s_tag2;
       for (int ps = 0; ps < P.lp.merge_passes; ps++) {
-        uint32_t run = Cs << ps;
+        uint32_t run = ch << ps;
         LAUNCH(PK_SAMPLE_MERGE, k_sample_merge<KW>, dim3((uint32_t)cdiv(P.m, MERGE_TILE)), dim3(NT), 0, st,
                            (const void*)so, (const uint32_t*)stg, so2, st2, (uint32_t)P.m, run);
         LAUNCH_CHECK();
@@ -608,9 +614,14 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       LAUNCH_CHECK();
       LAUNCH(PK_BUCKET_SORT, (k_bucket_sort_keys<KW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a, exp);
       LAUNCH_CHECK();
-      // few buckets are handed on: a small grid walks the list
-      LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<KW>), dim3((uint32_t)std::min<uint64_t>(lv.bkt_cap, 512)),
-             dim3(NT), 0, st, a);
+      // few buckets are handed on: small grids walk the lists (4-byte keys
+      // first try the round-based slot sort)
+      const uint32_t gl = (uint32_t)std::min<uint64_t>(lv.bkt_cap, 512);
+      if constexpr (KW == 4) {
+        LAUNCH(PK_BUCKET_LEFT, k_bucket_rounds_keys, dim3(std::min<uint32_t>(gl, 256)), dim3(WIDE_BNT), 0, st, a);
+        LAUNCH_CHECK();
+      }
+      LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<KW>), dim3(gl), dim3(NT), 0, st, a, KW == 4 ? 1 : 0);
     } else {
       if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
       else LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 256>), dim3(tiles), dim3(NT), 0, st, a);

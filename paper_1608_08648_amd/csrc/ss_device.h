@@ -326,4 +326,58 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t grid) {
   return start + i;
 }
 
+// ------------------------------------------------- work-group merge sort
+
+// Sorts the NTH*K u64 values a work-group holds (K per thread, in any
+// order) ascending.  Each thread first sorts its K values with an odd-even
+// transposition network; then log2(NTH) passes merge pairs of sorted runs
+// through LDS, each thread producing K consecutive outputs of its pair
+// (its starting point found by a binary search along the merge path).  On
+// return thread t holds sorted[t*K .. t*K+K) in v and buf holds the whole
+// sorted sequence (buf: NTH*K entries).
+template <int NTH, int K>
+__device__ __forceinline__ void block_merge_sort_u64(uint64_t (&v)[K], uint64_t* buf) {
+#pragma unroll
+  for (int pass = 0; pass < K; pass++) {
+#pragma unroll
+    for (int i = pass & 1; i + 1 < K; i += 2) {
+      const uint64_t a = v[i], b = v[i + 1];
+      v[i] = a < b ? a : b;
+      v[i + 1] = a < b ? b : a;
+    }
+  }
+  const int t = threadIdx.x;
+  for (int r = K; r < NTH * K; r *= 2) {
+#pragma unroll
+    for (int k = 0; k < K; k++) buf[t * K + k] = v[k];
+    __syncthreads();
+    const int tpg = 2 * r / K;               // threads per merged pair of runs
+    const int g = t / tpg, o = (t % tpg) * K;
+    const uint64_t* A = buf + g * 2 * r;
+    const uint64_t* B = A + r;
+    // a = number of A elements among the first o outputs (ties: A first)
+    int lo = o > r ? o - r : 0, hi = o < r ? o : r;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (A[mid] <= B[o - 1 - mid]) lo = mid + 1;
+      else hi = mid;
+    }
+    int ia = lo, ib = o - lo;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const bool ha = ia < r, hb = ib < r;
+      const uint64_t x = ha ? A[ia] : ~0ull;
+      const uint64_t y = hb ? B[ib] : ~0ull;
+      const bool takeA = ha && (!hb || x <= y);
+      v[k] = takeA ? x : y;
+      ia += takeA ? 1 : 0;
+      ib += takeA ? 0 : 1;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) buf[t * K + k] = v[k];
+  __syncthreads();
+}
+
 }  // namespace ss

@@ -48,6 +48,14 @@ template <int KW> struct SampleCap {
   static constexpr int C = NT * KMAX;
 };
 
+// Chunks of a sample too large for one work-group: sorted one per
+// work-group, then merged (4-byte keys: small chunks, so many work-groups
+// share the sort).
+template <int KW> struct SampleChunk {
+  static constexpr int K = (KW == 4) ? 8 : SampleCap<KW>::KMAX;
+  static constexpr int C = NT * K;
+};
+
 // Keys per thread in one chunk of the stable split.
 template <int KW, int VW> struct SplitChunk {
   static constexpr int KS = (KW + VW <= 4) ? 8 : 4;
@@ -92,6 +100,7 @@ struct Ctl {              // device control block at the start of the workspace
   uint32_t pad[2];
   LevelCtl lv[MAX_LEVELS];
   uint32_t nleft[MAX_LEVELS];   // buckets the slot sort handed on, per level
+  uint32_t nleft2[MAX_LEVELS];  // of those, buckets the round-based slot sort handed on
 };
 
 enum : uint32_t {
@@ -130,8 +139,10 @@ struct LevelArgs {
   uint64_t* exp_spl_ord;
   uint64_t* exp_spl_tag;
   uint64_t* exp_counts;
-  SmallEnt* left;          // buckets handed from the slot sort to the radix sort (keys only)
+  SmallEnt* left;          // buckets the slot sort handed on (keys only)
   uint32_t* nleft;
+  SmallEnt* left2;         // buckets the round-based slot sort handed on (4-byte keys only)
+  uint32_t* nleft2;
   uint32_t tile;           // keys per tile in the split passes
   uint32_t s;              // oversampling factor for automatically sized segments
   uint32_t p_cap;          // largest p for automatically sized segments
@@ -531,6 +542,29 @@ __device__ __forceinline__ void sample_sort_one(const LevelArgs& a, const SegDes
   const KT* so = (const KT*)a.s_ord + d.samp_off;
   const uint32_t* st = a.s_tag + d.samp_off;
   const int m = (int)d.m;
+  if constexpr (KW == 4) {
+    // 4-byte keys: (ord, tag) packed in a u64, merge-sorted in LDS
+    uint64_t v[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = t * K + k;
+      v[k] = i < m ? (((uint64_t)so[i] << 32) | st[i]) : ~0ull;
+    }
+    block_merge_sort_u64<NT, K>(v, sm.xh);
+    for (int i = t; i < m; i += NT) {
+      const uint64_t x = sm.xh[i];
+      ((KT*)a.s_ord)[d.samp_off + i] = (KT)(x >> 32);
+      a.s_tag[d.samp_off + i] = (uint32_t)x;
+      if (exp) { a.exp_smp_ord[i] = x >> 32; a.exp_smp_tag[i] = (uint32_t)x; }
+    }
+    for (uint32_t k = 1 + t; k < d.p; k += NT) {
+      const uint32_t r = eytz_rank(k, d.lgp);
+      const uint64_t x = sm.xh[r * d.stride - 1];
+      put_tree<KW>(a, d, k, (KT)(x >> 32), (uint32_t)x, exp);
+    }
+    __syncthreads();
+    return;
+  }
   uint64_t hi[K];
   uint32_t lo[K];
   NoVal nv[K];
@@ -599,8 +633,8 @@ template <int KW>
 __global__ void __launch_bounds__(NT) k_sample_chunk_sort(LevelArgs a) {
   __shared__ SampleLds<KW> sm;
   using KT = typename KeyOf<KW>::T;
-  constexpr int KM = SampleLds<KW>::KMAX;
-  constexpr int C = NT * KM;
+  constexpr int KM = SampleChunk<KW>::K;
+  constexpr int C = SampleChunk<KW>::C;
   SegDesc d = a.segs[0];
   uint32_t cb = blockIdx.x * C;
   if (cb >= d.m) return;
@@ -1318,16 +1352,18 @@ __global__ void __launch_bounds__(NT) k_bucket_sort_keys(LevelArgs a, int export
   }
 }
 
-// Keys only: buckets the slot sort handed on -- radix sort in LDS, or the
-// next level / fallback when larger than one work-group.
+// Keys only: buckets handed on by the slot sorts (list 0: by the slot sort,
+// list 1: by the round-based one) -- radix sort in LDS, or the next level /
+// fallback when larger than one work-group.
 template <int KW>
-__global__ void __launch_bounds__(NT) k_bucket_leftover_keys(LevelArgs a) {
+__global__ void __launch_bounds__(NT) k_bucket_leftover_keys(LevelArgs a, int list) {
   using KT = typename KeyOf<KW>::T;
   constexpr uint32_t C = SmallCap<KW, 0>::C;
   __shared__ SmallLds<KW, 0, SmallCap<KW, 0>::KMAX> sm;
-  const uint32_t nl = *a.nleft;
+  const SmallEnt* left = list ? a.left2 : a.left;
+  const uint32_t nl = list ? *a.nleft2 : *a.nleft;
   for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
-    const SmallEnt e = a.left[li];
+    const SmallEnt e = left[li];
     if (e.len <= C) {
       sort_small<KW, 0>((const KT*)a.dst, nullptr, (KT*)a.out, nullptr, e.beg, e.len, 0, 0, a.kout, sm);
       continue;

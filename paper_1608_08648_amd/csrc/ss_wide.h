@@ -635,4 +635,26 @@ __global__ void __launch_bounds__(WIDE_BNT) k_wide_bucket(LevelArgs a, WideArgs 
   }
 }
 
+// Keys only, 4-byte keys: buckets the slot sort of a level handed on (too
+// large for it, or crowded) get the round-based slot sort; what that cannot
+// take goes on to the radix sort's list.
+__global__ void __launch_bounds__(WIDE_BNT) k_bucket_rounds_keys(LevelArgs a) {
+  __shared__ SlotRoundsLds<WIDE_BCAP> sm;
+  const uint32_t nl = *a.nleft;
+  for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+    const SmallEnt e = a.left[li];
+    const bool done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP>((const uint32_t*)a.dst + e.beg, (uint32_t*)a.out + e.beg,
+                                                             e.len, a.kout, sm, false, 0u, false, 0u);
+    if (threadIdx.x == 0) {
+      if (done) {
+        atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)e.len);
+      } else {
+        const uint32_t k = atomicAdd(a.nleft2, 1u);
+        a.left2[k] = e;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace ss
