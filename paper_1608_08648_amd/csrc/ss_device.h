@@ -326,6 +326,39 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t grid) {
   return start + i;
 }
 
+// ------------------------------------------------- LDS counters
+
+// LDS atomic increments by the active lanes of a wave, each on counter
+// cnt[b].  When every active lane has the same b (sorted or constant input),
+// one atomic serves the whole wave instead of 64 on one address.
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// cnt[b] += 1 per active lane
+__device__ __forceinline__ void lds_count(uint32_t* cnt, uint32_t b) {
+  const uint64_t act = __ballot(1);
+  const uint32_t first = __builtin_amdgcn_readfirstlane(b);
+  if (__ballot(b == first) == act) {
+    if (lane_rank(act) == 0) atomicAdd(&cnt[b], (uint32_t)__popcll(act));
+  } else {
+    atomicAdd(&cnt[b], 1u);
+  }
+}
+
+// old = cnt[b]++ per active lane (distinct slots; order among lanes free)
+__device__ __forceinline__ uint32_t lds_claim(uint32_t* cnt, uint32_t b) {
+  const uint64_t act = __ballot(1);
+  const uint32_t first = __builtin_amdgcn_readfirstlane(b);
+  if (__ballot(b == first) == act) {
+    const uint32_t r = lane_rank(act);
+    uint32_t base = 0;
+    if (r == 0) base = atomicAdd(&cnt[b], (uint32_t)__popcll(act));
+    return __builtin_amdgcn_readfirstlane(base) + r;
+  }
+  return atomicAdd(&cnt[b], 1u);
+}
+
 // ------------------------------------------------- work-group merge sort
 
 // Sorts the NTH*K u64 values a work-group holds (K per thread, in any

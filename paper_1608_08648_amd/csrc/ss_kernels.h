@@ -1064,9 +1064,19 @@ __device__ __forceinline__ void split_chunk(const LevelArgs& a, const SegDesc& d
     key[u] = (FULL || i < cn) ? to_ord(src[c0 + i], a.kin) : KT(0);
   }
   sm.tr.template classify_many<U>(key, tag, d.lgp, d.p, b);
+  // sorted or constant input puts a wave's row of 64 keys into one bucket:
+  // then (tested on the first row) each row claims its slots with one
+  // atomic instead of 64 on one address
+  const bool rows = __ballot(b[0] == __builtin_amdgcn_readfirstlane(b[0])) == __ballot(1);
+  if (rows) {
 #pragma unroll
-  for (int u = 0; u < U; u++)
-    if (FULL || (uint32_t)(u * NT + t) < cn) atomicAdd(&sm.cur[x][b[u]], 1u);
+    for (int u = 0; u < U; u++)
+      if (FULL || (uint32_t)(u * NT + t) < cn) lds_count(sm.cur[x], b[u]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; u++)
+      if (FULL || (uint32_t)(u * NT + t) < cn) atomicAdd(&sm.cur[x][b[u]], 1u);
+  }
   __syncthreads();
   // close the previous chunk's bookkeeping, then chunk starts of this one
   {
@@ -1096,12 +1106,23 @@ __device__ __forceinline__ void split_chunk(const LevelArgs& a, const SegDesc& d
     }
   }
   __syncthreads();
+  if (rows) {
 #pragma unroll
-  for (int u = 0; u < U; u++) {
-    if (FULL || (uint32_t)(u * NT + t) < cn) {
-      uint32_t pos = atomicAdd(&sm.cur[x][b[u]], 1u);
-      sm.sk[pos] = key[u];
-      sm.sb[pos] = (BT)b[u];
+    for (int u = 0; u < U; u++) {
+      if (FULL || (uint32_t)(u * NT + t) < cn) {
+        uint32_t pos = lds_claim(sm.cur[x], b[u]);
+        sm.sk[pos] = key[u];
+        sm.sb[pos] = (BT)b[u];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (FULL || (uint32_t)(u * NT + t) < cn) {
+        uint32_t pos = atomicAdd(&sm.cur[x][b[u]], 1u);
+        sm.sk[pos] = key[u];
+        sm.sb[pos] = (BT)b[u];
+      }
     }
   }
   __syncthreads();

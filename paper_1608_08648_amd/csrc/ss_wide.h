@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
   if (threadIdx.x == 0) *w.hdr = WideHdr{kmin, kmax, sh, ncell};
 }
 
-// Search of one key among the candidates of its cell, on the key alone.
+// Search of one key among the candidates of its cell, on the key alone:
 // lo - 1 = #{splitters whose key < key}; tie = some splitter has this key
 // (then it is splitter lo: the first with key >= key is always compared).
 __device__ __forceinline__ uint32_t wide_lower(const uint32_t* sk, const uint32_t* cells, const WideHdr& h,
@@ -122,6 +122,17 @@ __device__ __forceinline__ uint32_t wide_lower(const uint32_t* sk, const uint32_
   if (key > h.kmax) return p;
   const uint32_t cell = cells[(key - h.kmin) >> h.sh];
   uint32_t lo = (cell & 0xFFFFu) + 1, len = (cell >> 16) - (cell & 0xFFFFu);
+  if (len > 4) {
+    // many candidates (runs of equal splitter keys): the first one settles
+    // keys below all of them and keys equal to it at once
+    const uint32_t v0 = sk[lo];
+    if (v0 >= key) {
+      tie = v0 == key;
+      return lo;
+    }
+    lo++;
+    len--;
+  }
   uint32_t hk = ~key;
   while (len) {
     const uint32_t half = len >> 1, m = lo + half, v = sk[m];
@@ -141,8 +152,9 @@ __device__ __forceinline__ uint32_t wide_lower(const uint32_t* sk, const uint32_
 // b = (lo - 1) + #{r >= lo : (sk[r], st[r]) < (key, tag)}; tie-low when
 // splitter b has the key, else tie-high (splitter b + 1 = lo has it).
 __device__ __forceinline__ uint32_t wide_tie_bucket(const uint32_t* sk, const uint32_t* st, uint32_t p, uint32_t lo,
-                                                    uint32_t key, uint32_t tag, uint32_t& kind) {
-  uint32_t a = lo, z = p;                   // first r in [lo, p) with (sk, st)[r] >= (key, tag)
+                                                    uint32_t up, uint32_t key, uint32_t tag, uint32_t& kind) {
+  uint32_t a = lo, z = up + 1;              // first r in [lo, up + 1) with (sk, st)[r] >= (key, tag)
+  (void)p;
   while (a < z) {
     const uint32_t m = (a + z) / 2;
     if (sk[m] == key && st[m] < tag) a = m + 1;
@@ -214,6 +226,7 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
   if (t < (int)WIDE_P1) sm.csum[t] = 0;
   __syncthreads();
   uint32_t cur = ~0u, run = 0;       // run of equal (kind << 16 | bucket)
+  uint32_t hint = ~0u;               // bucket of this thread's previous tie key
   auto flush = [&]() {
     if (!run) return;
     const uint32_t kind = cur >> 16, b = cur & 0xFFFFu;
@@ -232,7 +245,26 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
         bool tie;
         const uint32_t lo = wide_lower(sm.sk, sm.cells, h, p, key[u], tie);
         uint32_t b = lo - 1, kind = 0;
-        if (tie) b = wide_tie_bucket(sm.sk, sm.st, p, lo, key[u], i, kind);
+        if (tie) {
+          // equal keys in input order mostly share a bucket: try the last one
+          const uint32_t k = key[u];
+          const uint32_t hb = hint;
+          bool hit = false;
+          if (hb != ~0u && hb + 1 >= lo) {
+            const bool above = hb == 0 || sm.sk[hb] < k || (sm.sk[hb] == k && sm.st[hb] < i);
+            const bool below = hb + 1 == p || k < sm.sk[hb + 1] || (k == sm.sk[hb + 1] && i < sm.st[hb + 1]);
+            hit = above && below;
+          }
+          if (hit) {
+            b = hb;
+            kind = (hb > 0 && sm.sk[hb] == k) ? 1u : 2u;
+          } else {
+            // every splitter with this key lies in the key's cell: [lo, up]
+            const uint32_t up = sm.cells[(k - h.kmin) >> h.sh] >> 16;
+            b = wide_tie_bucket(sm.sk, sm.st, p, lo, up, k, i, kind);
+          }
+          hint = b;
+        }
         const uint32_t idx = (kind << 16) | b;
         if (idx != cur) {
           flush();
@@ -280,9 +312,19 @@ template <int NB>
 __device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uint32_t (&key)[WIDE_U],
                                                  const uint32_t (&bk)[WIDE_U], uint32_t* dst, int x, bool first) {
   const int t = threadIdx.x;
+  // sorted or constant input puts a wave's row of 64 keys into one bucket:
+  // then (tested on the first row) each row claims its slots with one
+  // atomic instead of 64 on one address
+  const bool rows = __ballot(bk[0] == __builtin_amdgcn_readfirstlane(bk[0])) == __ballot(1);
+  if (rows) {
 #pragma unroll
-  for (int u = 0; u < WIDE_U; u++)
-    if (bk[u] != ~0u) atomicAdd(&sm.cur[x][bk[u]], 1u);
+    for (int u = 0; u < WIDE_U; u++)
+      if (bk[u] != ~0u) lds_count(sm.cur[x], bk[u]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++)
+      if (bk[u] != ~0u) atomicAdd(&sm.cur[x][bk[u]], 1u);
+  }
   __syncthreads();
   // close the previous chunk's bookkeeping, then chunk starts of this one
   // (NB <= 64: one wave)
@@ -299,12 +341,23 @@ __device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uin
     if (t == NB - 1) sm.ctot[x] = inc;
   }
   __syncthreads();
+  if (rows) {
 #pragma unroll
-  for (int u = 0; u < WIDE_U; u++) {
-    if (bk[u] != ~0u) {
-      const uint32_t pos = atomicAdd(&sm.cur[x][bk[u]], 1u);
-      sm.sk[pos] = key[u];
-      sm.sb[pos] = (uint8_t)bk[u];
+    for (int u = 0; u < WIDE_U; u++) {
+      if (bk[u] != ~0u) {
+        const uint32_t pos = lds_claim(sm.cur[x], bk[u]);
+        sm.sk[pos] = key[u];
+        sm.sb[pos] = (uint8_t)bk[u];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) {
+      if (bk[u] != ~0u) {
+        const uint32_t pos = atomicAdd(&sm.cur[x][bk[u]], 1u);
+        sm.sk[pos] = key[u];
+        sm.sb[pos] = (uint8_t)bk[u];
+      }
     }
   }
   __syncthreads();
@@ -451,8 +504,8 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
 // sort of the level kernels: slot(key) = (key - lo) >> sh over S = 8192
 // slots, count, scan, place, then order each slot's few keys.  A bucket
 // larger than the LDS is handled in rounds: round r places the keys of the
-// slots whose start lies in [r*C', (r+1)*C'), C' = CAP - SLOT_MAX_FILL, so a
-// round never holds more than CAP keys.  Each round re-reads the bucket
+// slots whose start lies in [r*C', (r+1)*C'), C' = CAP - ROUNDS_MAX_FILL, so
+// a round never holds more than CAP keys.  Each round re-reads the bucket
 // (from L2).  Returns false (having written nothing) when a slot is too
 // crowded or the bucket too large.
 template <int CAP>
@@ -464,12 +517,16 @@ struct SlotRoundsLds {
   uint32_t rslot[8], rbase[8];    // first slot and first position of each round
 };
 
+// (crowded: a slot of more than ROUNDS_MAX_FILL keys, whose ranking would
+// cost that many steps per key)
+constexpr uint32_t ROUNDS_MAX_FILL = 256;
+
 template <int NTH, int CAP>
 __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* out, uint32_t len, int kout,
                                                  SlotRoundsLds<CAP>& sm, bool lo_known, uint32_t lo, bool hi_known,
                                                  uint32_t hi) {
   constexpr int S = 1 << SLOT_LOG2;
-  constexpr uint32_t CR = CAP - SLOT_MAX_FILL;
+  constexpr uint32_t CR = CAP - ROUNDS_MAX_FILL;
   const int t = threadIdx.x;
   if (len > 65535u) return false;
   uint32_t mn = ~0u, mx = 0;
@@ -525,7 +582,7 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
     uint32_t wm = wave_max(mxc);
     if (t == 0) sm.flag = 0;
     __syncthreads();
-    if (lane_id() == 0 && wm > SLOT_MAX_FILL) atomicOr(&sm.flag, 1u);
+    if (lane_id() == 0 && wm > ROUNDS_MAX_FILL) atomicOr(&sm.flag, 1u);
 #pragma unroll
     for (int j = 0; j < PER; j++) {
       sm.cnt[t * PER + j] = run;
