@@ -1174,6 +1174,27 @@ __global__ void __launch_bounds__(NT) k_scatter_keys(LevelArgs a) {
 // two per word.  Returns false (having written nothing) when a slot is too
 // crowded; the caller then radix-sorts.
 // LDS of the slot sort stays under 80 KB so two work-groups share a CU.
+// Rank phase of the slot sorts: placed[0, len) holds the keys grouped by
+// slot; bounds(k, s0, s1) gives the range of k's slot.  A key's final
+// position = s0 + #{keys of its slot that are smaller, or equal and placed
+// earlier}.
+template <int KW, int NTH, typename F>
+__device__ __forceinline__ void slot_rank_write(const typename KeyOf<KW>::T* placed, uint32_t len,
+                                                typename KeyOf<KW>::T* out, int kout, F bounds) {
+  using KT = typename KeyOf<KW>::T;
+  for (uint32_t i = threadIdx.x; i < len; i += NTH) {
+    const KT k = placed[i];
+    uint32_t s0, s1;
+    bounds(k, s0, s1);
+    uint32_t rank = 0;
+    for (uint32_t j = s0; j < s1; j++) {
+      const KT o = placed[j];
+      rank += (o < k || (o == k && j < i)) ? 1u : 0u;
+    }
+    out[s0 + rank] = from_ord(k, kout);
+  }
+}
+
 template <int KW> struct SlotCap { static constexpr int C = KW == 4 ? 16128 : 8064; };
 constexpr int SLOT_LOG2 = 13;                   // S = 8192 slots
 constexpr uint32_t SLOT_MAX_FILL = 48;          // crowded-slot limit
@@ -1277,6 +1298,12 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
   __syncthreads();
   if (crowded) return false;
   // place: afterwards each slot's counter holds the slot's end
+  auto place = [&](KT k) {
+    const uint32_t q = slot(k);
+    const uint32_t sft = 16 * (q & 1);
+    const uint32_t old = atomicAdd(&sm.scnt[q >> 1], 1u << sft);
+    sm.placed[(old >> sft) & 0xFFFFu] = k;
+  };
   for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
     KT k[8];
 #pragma unroll
@@ -1285,30 +1312,18 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
       k[u] = i < len ? to_ord(in[i], kin) : KT(0);
     }
 #pragma unroll
-    for (int u = 0; u < 8; u++) {
-      if (i0 + u * NTH + t < len) {
-        uint32_t q = slot(k[u]);
-        uint32_t sft = 16 * (q & 1);
-        uint32_t old = atomicAdd(&sm.scnt[q >> 1], 1u << sft);
-        sm.placed[(old >> sft) & 0xFFFFu] = k[u];
-      }
-    }
+    for (int u = 0; u < 8; u++)
+      if (i0 + u * NTH + t < len) place(k[u]);
   }
   __syncthreads();
   // order each slot: a key's rank = keys of its slot that are smaller, or
   // equal and placed earlier
   auto slot_end = [&](uint32_t q) { return (sm.scnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu; };
-  for (uint32_t i = t; i < len; i += NTH) {
-    KT k = sm.placed[i];
-    uint32_t q = slot(k);
-    uint32_t s0 = q ? slot_end(q - 1) : 0u, s1 = slot_end(q);
-    uint32_t rank = 0;
-    for (uint32_t j = s0; j < s1; j++) {
-      KT o = sm.placed[j];
-      rank += (o < k || (o == k && j < i)) ? 1u : 0u;
-    }
-    out[beg + s0 + rank] = from_ord(k, kout);
-  }
+  slot_rank_write<KW, NTH>(sm.placed, len, out + beg, kout, [&](KT k, uint32_t& s0, uint32_t& s1) {
+    const uint32_t q = slot(k);
+    s0 = q ? slot_end(q - 1) : 0u;
+    s1 = slot_end(q);
+  });
   __syncthreads();
   return true;
 }

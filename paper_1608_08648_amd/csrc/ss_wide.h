@@ -501,17 +501,19 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
 }
 
 // Slot sort of up to 65535 keys in rounds (4-byte ord keys).  As the slot
-// sort of the level kernels: slot(key) = (key - lo) >> sh over S = 8192
+// sort of the level kernels: slot(key) = (key - lo) >> sh over S = 16384
 // slots, count, scan, place, then order each slot's few keys.  A bucket
 // larger than the LDS is handled in rounds: round r places the keys of the
 // slots whose start lies in [r*C', (r+1)*C'), C' = CAP - ROUNDS_MAX_FILL, so
 // a round never holds more than CAP keys.  Each round re-reads the bucket
 // (from L2).  Returns false (having written nothing) when a slot is too
 // crowded or the bucket too large.
+constexpr int ROUNDS_LOG2 = 14;   // S = 16384 slots: about one key per slot for 16K-key buckets
+
 template <int CAP>
 struct SlotRoundsLds {
   uint32_t placed[CAP];
-  uint32_t cnt[1 << SLOT_LOG2];   // counts, then slot starts, then slot cursors / ends
+  uint32_t cnt[(1 << ROUNDS_LOG2) / 2];   // 16-bit slot counts, then starts, then cursors / ends, two per word
   alignas(8) uint64_t red[64];
   uint32_t flag;
   uint32_t rslot[8], rbase[8];    // first slot and first position of each round
@@ -525,10 +527,11 @@ template <int NTH, int CAP>
 __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* out, uint32_t len, int kout,
                                                  SlotRoundsLds<CAP>& sm, bool lo_known, uint32_t lo, bool hi_known,
                                                  uint32_t hi) {
-  constexpr int S = 1 << SLOT_LOG2;
+  constexpr int S = 1 << ROUNDS_LOG2;
+  constexpr int W = S / 2;
   constexpr uint32_t CR = CAP - ROUNDS_MAX_FILL;
   const int t = threadIdx.x;
-  if (len > 65535u) return false;
+  if (len > 65535u) return false;          // (16-bit counters and positions)
   uint32_t mn = ~0u, mx = 0;
   if (!(lo_known && hi_known)) {
     for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
@@ -543,7 +546,7 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
         if (i0 + u * NTH + t < len) { mn = k[u] < mn ? k[u] : mn; mx = k[u] > mx ? k[u] : mx; }
     }
   }
-  for (int q = t; q < S; q += NTH) sm.cnt[q] = 0;
+  for (int q = t; q < W; q += NTH) sm.cnt[q] = 0;
   if (!(lo_known && hi_known)) block_minmax<NTH>(mn, mx, (uint32_t*)sm.red);   // (ends with a barrier)
   else __syncthreads();
   if (lo_known) mn = lo;
@@ -553,8 +556,9 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
     return true;
   }
   const int bw = bit_width<uint32_t>(mx - mn);
-  const int sh = bw > SLOT_LOG2 ? bw - SLOT_LOG2 : 0;
+  const int sh = bw > ROUNDS_LOG2 ? bw - ROUNDS_LOG2 : 0;
   auto slot = [&](uint32_t k) { return (k - mn) >> sh; };
+  auto get = [&](uint32_t q) { return (sm.cnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu; };
   for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
     uint32_t k[8];
 #pragma unroll
@@ -563,19 +567,24 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
       k[u] = i < len ? in[i] : 0u;
     }
 #pragma unroll
-    for (int u = 0; u < 8; u++)
-      if (i0 + u * NTH + t < len) atomicAdd(&sm.cnt[slot(k[u])], 1u);
+    for (int u = 0; u < 8; u++) {
+      if (i0 + u * NTH + t < len) {
+        const uint32_t q = slot(k[u]);
+        atomicAdd(&sm.cnt[q >> 1], 1u << (16 * (q & 1)));
+      }
+    }
   }
   __syncthreads();
-  // exclusive scan of the slot counts, and the fullest slot
+  // exclusive scan of the slot counts (16-bit halves), and the fullest slot
   {
-    constexpr int PER = S / NTH;
+    constexpr int PER = W / NTH;
     uint32_t v[PER], sum = 0, mxc = 0;
 #pragma unroll
     for (int j = 0; j < PER; j++) {
       v[j] = sm.cnt[t * PER + j];
-      sum += v[j];
-      mxc = max(mxc, v[j]);
+      const uint32_t a0 = v[j] & 0xFFFFu, a1 = v[j] >> 16;
+      sum += a0 + a1;
+      mxc = max(mxc, max(a0, a1));
     }
     uint32_t tot;
     uint32_t run = block_excl_scan<NTH>(sum, (uint32_t*)sm.red, &tot);
@@ -585,8 +594,9 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
     if (lane_id() == 0 && wm > ROUNDS_MAX_FILL) atomicOr(&sm.flag, 1u);
 #pragma unroll
     for (int j = 0; j < PER; j++) {
-      sm.cnt[t * PER + j] = run;
-      run += v[j];
+      const uint32_t a0 = v[j] & 0xFFFFu;
+      sm.cnt[t * PER + j] = run | ((run + a0) << 16);   // starts of slots 2w and 2w+1
+      run += a0 + (v[j] >> 16);
     }
   }
   __syncthreads();
@@ -598,23 +608,31 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
     uint32_t a = 0, z = S;
     while (a < z) {
       uint32_t m = (a + z) / 2;
-      if (sm.cnt[m] < x) a = m + 1;
+      if (get(m) < x) a = m + 1;
       else z = m;
     }
     return a;
   };
-  // round boundaries, taken while cnt still holds the slot starts
+  // round boundaries, taken while the counters still hold the slot starts
   // (len < 2^16 and CR > 2^14: at most four rounds)
   const uint32_t rounds = (len + CR - 1) / CR;
   if (t <= (int)rounds) {
     const uint32_t b = (t == 0) ? 0u : ((uint32_t)t < rounds ? first_slot(t * CR) : (uint32_t)S);
     sm.rslot[t] = b;
-    sm.rbase[t] = b < (uint32_t)S ? sm.cnt[b] : len;
+    sm.rbase[t] = b < (uint32_t)S ? get(b) : len;
   }
   __syncthreads();
   for (uint32_t r = 0; r < rounds; r++) {
     // slots [qa, qb) of this round; slots below qa already hold their ends
     const uint32_t qa = sm.rslot[r], qb = sm.rslot[r + 1], base = sm.rbase[r];
+    auto place = [&](uint32_t k) {
+      const uint32_t q = slot(k);
+      if (rounds == 1 || (q >= qa && q < qb)) {
+        const uint32_t sft = 16 * (q & 1);
+        const uint32_t old = atomicAdd(&sm.cnt[q >> 1], 1u << sft);
+        sm.placed[((old >> sft) & 0xFFFFu) - base] = k;
+      }
+    };
     for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
       uint32_t k[8];
 #pragma unroll
@@ -623,28 +641,17 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
         k[u] = i < len ? in[i] : 0u;
       }
 #pragma unroll
-      for (int u = 0; u < 8; u++) {
-        if (i0 + u * NTH + t < len) {
-          const uint32_t q = slot(k[u]);
-          if (q >= qa && q < qb) sm.placed[atomicAdd(&sm.cnt[q], 1u) - base] = k[u];
-        }
-      }
+      for (int u = 0; u < 8; u++)
+        if (i0 + u * NTH + t < len) place(k[u]);
     }
     __syncthreads();
-    // order each slot: a key's rank = keys of its slot that are smaller, or
-    // equal and placed earlier (cnt[q] is now the end of slot q for q < qb)
-    const uint32_t top = (qb < (uint32_t)S ? sm.cnt[qb - 1] : len) - base;
-    for (uint32_t i = t; i < top; i += NTH) {
-      const uint32_t k = sm.placed[i];
+    // order each slot (the counter of slot q < qb now holds its end)
+    const uint32_t top = (qb < (uint32_t)S ? get(qb - 1) : len) - base;
+    slot_rank_write<4, NTH>(sm.placed, top, out + base, kout, [&](uint32_t k, uint32_t& s0, uint32_t& s1) {
       const uint32_t q = slot(k);
-      const uint32_t s0 = (q ? sm.cnt[q - 1] : 0u) - base, s1 = sm.cnt[q] - base;
-      uint32_t rank = 0;
-      for (uint32_t j = s0; j < s1; j++) {
-        const uint32_t o = sm.placed[j];
-        rank += (o < k || (o == k && j < i)) ? 1u : 0u;
-      }
-      out[base + s0 + rank] = from_ord(k, kout);
-    }
+      s0 = (q ? get(q - 1) : 0u) - base;
+      s1 = get(q) - base;
+    });
     __syncthreads();
   }
   return true;
