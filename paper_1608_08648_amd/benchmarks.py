@@ -37,6 +37,19 @@ def _timed(fn, steps, warmup, stream=None):
     return e0.elapsed_time(e1) / steps
 
 
+def _kernel_table(fn, steps):
+    """Per-kernel HIP-event times of `steps` extra calls (every launch
+    bracketed; outside any timed region)."""
+    N.profile_enable(True, max_launches=256 * (steps + 1))
+    for _ in range(steps):
+        fn()
+    N.profile_collect()
+    rep = N.profile_report()
+    N.profile_enable(False)
+    return {k: {"ms_per_step": round(ms / steps, 5), "launches_per_step": round(c / steps, 3)}
+            for k, (ms, c) in rep.items() if c}
+
+
 def _base(metric, value, unit, args, ms, dtype, config, **extra):
     d = {"metric": metric, "value": round(value, 4), "unit": unit, "n_gpus": 1, "steps": args.steps,
          "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
@@ -59,6 +72,7 @@ def bench_pairs(args):
         api.sort_pairs(kd, vd, prm=prm, keys_out=ko, vals_out=vo, ws=ws, key_type="u64")
 
     ms = _timed(step, args.steps, args.warmup)
+    kernels = _kernel_table(step, max(1, min(args.steps, 5)))
     ko_h = ko.cpu().numpy().view(np.uint64)
     vo_h = vo.cpu().numpy().view(np.uint32)
     # stable: sorted keys, and payload (= input index) strictly increasing inside runs of equal keys
@@ -70,7 +84,7 @@ def bench_pairs(args):
                  ms, "u64+u32",
                  {"workload": "2^27 uint64 keys uniform on [0, 0.7n) with uint32 payload = index, stable",
                   "p": prm.p, "s": prm.s, "seed": seed},
-                 hbm_frac_56B_per_pair=round(gp * 56 / HBM_PEAK_GBS, 4),
+                 hbm_frac_56B_per_pair=round(gp * 56 / HBM_PEAK_GBS, 4), kernels=kernels,
                  check="stable order (sorted, payload increasing in equal-key runs, payload indexes the key)"
                  if ok else "FAILED"), ok
 

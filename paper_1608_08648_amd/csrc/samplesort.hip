@@ -522,17 +522,19 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   const uint64_t nf = (uint64_t)w.p * (w.W + 2) + 1, na = (uint64_t)WIDE_P1 * w.W + 1;
   uint32_t* pf = (uint32_t*)(ws + P.o_whf_part);
   uint32_t* pa = (uint32_t*)(ws + P.o_wha_part);
-  LAUNCH(PK_INIT, k_wide_zero, dim3(grid_of(w.p, 256, 64)), dim3(256), 0, st, w);
   LAUNCH(PK_TREE, k_wide_table, dim3(1), dim3(NT), 0, st, w);
   LAUNCH(PK_CLASSIFY, k_wide_count, dim3(w.W), dim3(NT), 0, st, w);
   LAUNCH_CHECK();
   const uint32_t nbf = (uint32_t)cdiv(nf, SCAN_BLOCK), nba = (uint32_t)cdiv(na, SCAN_BLOCK);
-  LAUNCH(PK_SCAN, k_scan_reduce, dim3(nbf), dim3(NT), 0, st, (const uint32_t*)w.hf, pf, nf, (const uint64_t*)nullptr);
-  LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, pf, nf, (const uint64_t*)nullptr);
-  LAUNCH(PK_SCAN, k_scan_down, dim3(nbf), dim3(NT), 0, st, w.hf, (const uint32_t*)pf, nf, (const uint64_t*)nullptr);
-  LAUNCH(PK_SCAN, k_scan_reduce, dim3(nba), dim3(NT), 0, st, (const uint32_t*)w.ha, pa, na, (const uint64_t*)nullptr);
-  LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, pa, na, (const uint64_t*)nullptr);
-  LAUNCH(PK_SCAN, k_scan_down, dim3(nba), dim3(NT), 0, st, w.ha, (const uint32_t*)pa, na, (const uint64_t*)nullptr);
+  // both count arrays in one set of scan launches
+  ScanPair q;
+  q.h2 = w.ha;
+  q.part2 = pa;
+  q.total2 = na;
+  q.nb1 = nbf;
+  LAUNCH(PK_SCAN, k_scan_reduce, dim3(nbf + nba), dim3(NT), 0, st, w.hf, pf, nf, (const uint64_t*)nullptr, q);
+  LAUNCH(PK_SCAN, k_scan_partials, dim3(2), dim3(NT), 0, st, pf, nf, (const uint64_t*)nullptr, q);
+  LAUNCH(PK_SCAN, k_scan_down, dim3(nbf + nba), dim3(NT), 0, st, w.hf, pf, nf, (const uint64_t*)nullptr, q);
   LAUNCH_CHECK();
   LAUNCH(PK_SPLIT_COARSE, k_wide_split_a, dim3(w.W), dim3(NT), 0, st, w);
   LAUNCH_CHECK();
@@ -601,11 +603,10 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
     LAUNCH_CHECK();
     const uint32_t nb = (uint32_t)cdiv(std::max<uint64_t>(lv.hist_cap, 1), SCAN_BLOCK);
     const uint64_t* tot_dev = &a.ctl->total_hist;
-    LAUNCH(PK_SCAN, k_scan_reduce, dim3(nb), dim3(NT), 0, st, (const uint32_t*)a.hist, a.scan_part, (uint64_t)0,
-           tot_dev);
-    LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, a.scan_part, (uint64_t)0, tot_dev);
-    LAUNCH(PK_SCAN, k_scan_down, dim3(nb), dim3(NT), 0, st, a.hist, (const uint32_t*)a.scan_part, (uint64_t)0,
-           tot_dev);
+    LAUNCH(PK_SCAN, k_scan_reduce, dim3(nb), dim3(NT), 0, st, a.hist, a.scan_part, (uint64_t)0, tot_dev,
+           ScanPair{});
+    LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, a.scan_part, (uint64_t)0, tot_dev, ScanPair{});
+    LAUNCH(PK_SCAN, k_scan_down, dim3(nb), dim3(NT), 0, st, a.hist, a.scan_part, (uint64_t)0, tot_dev, ScanPair{});
     LAUNCH_CHECK();
     if constexpr (VW == 0) {
       // keys only: equal keys are bit-identical, so placement order inside a bucket is free

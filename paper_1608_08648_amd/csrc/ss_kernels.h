@@ -802,11 +802,30 @@ __device__ __forceinline__ uint64_t scan_len(uint64_t total, const uint64_t* tot
   return total_dev ? *total_dev : total;
 }
 
-__global__ void __launch_bounds__(NT) k_scan_reduce(const uint32_t* h, uint32_t* part, uint64_t total_h,
-                                                    const uint64_t* total_dev) {
+// Up to two arrays per launch: blocks [0, nb1) scan array 1 (h, part,
+// total), the rest array 2 (h2, part2, total2; total2 given on the host).
+struct ScanPair {
+  uint32_t* h2 = nullptr;
+  uint32_t* part2 = nullptr;
+  uint64_t total2 = 0;
+  uint32_t nb1 = 0xFFFFFFFFu;
+};
+
+__device__ __forceinline__ uint32_t scan_pick(uint32_t*& h, uint32_t*& part, uint64_t& total, const ScanPair& q,
+                                              uint32_t bid) {
+  if (bid < q.nb1) return bid;
+  h = q.h2;
+  part = q.part2;
+  total = q.total2;
+  return bid - q.nb1;
+}
+
+__global__ void __launch_bounds__(NT) k_scan_reduce(uint32_t* h, uint32_t* part, uint64_t total_h,
+                                                    const uint64_t* total_dev, ScanPair q) {
   __shared__ uint32_t sh[NT / WAVE + 2];
-  const uint64_t total = scan_len(total_h, total_dev);
-  uint64_t b0 = (uint64_t)blockIdx.x * SCAN_BLOCK;
+  uint64_t total = scan_len(total_h, total_dev);
+  const uint32_t bid = scan_pick(h, part, total, q, blockIdx.x);
+  uint64_t b0 = (uint64_t)bid * SCAN_BLOCK;
   if (b0 >= total) return;
   uint32_t s = 0;
   for (int r = 0; r < SCAN_ITEMS; r++) {
@@ -815,12 +834,15 @@ __global__ void __launch_bounds__(NT) k_scan_reduce(const uint32_t* h, uint32_t*
   }
   uint32_t tot;
   block_excl_scan<NT>(s, sh, &tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  if (threadIdx.x == 0) part[bid] = tot;
 }
 
-__global__ void __launch_bounds__(NT) k_scan_partials(uint32_t* part, uint64_t total_h, const uint64_t* total_dev) {
+__global__ void __launch_bounds__(NT) k_scan_partials(uint32_t* part, uint64_t total_h, const uint64_t* total_dev,
+                                                      ScanPair q) {
   __shared__ uint32_t sh[NT / WAVE + 2];
-  const uint64_t total = scan_len(total_h, total_dev);
+  uint64_t total = scan_len(total_h, total_dev);
+  uint32_t* hh = nullptr;
+  if (blockIdx.x == 1) scan_pick(hh, part, total, q, q.nb1);
   const uint32_t nb = (uint32_t)((total + SCAN_BLOCK - 1) / SCAN_BLOCK);
   uint32_t run = 0;
   for (uint32_t base = 0; base < nb; base += NT) {
@@ -833,11 +855,12 @@ __global__ void __launch_bounds__(NT) k_scan_partials(uint32_t* part, uint64_t t
   }
 }
 
-__global__ void __launch_bounds__(NT) k_scan_down(uint32_t* h, const uint32_t* part, uint64_t total_h,
-                                                  const uint64_t* total_dev) {
+__global__ void __launch_bounds__(NT) k_scan_down(uint32_t* h, uint32_t* part, uint64_t total_h,
+                                                  const uint64_t* total_dev, ScanPair q) {
   __shared__ uint32_t sh[NT / WAVE + 2];
-  const uint64_t total = scan_len(total_h, total_dev);
-  uint64_t b0 = (uint64_t)blockIdx.x * SCAN_BLOCK;
+  uint64_t total = scan_len(total_h, total_dev);
+  const uint32_t bid = scan_pick(h, part, total, q, blockIdx.x);
+  uint64_t b0 = (uint64_t)bid * SCAN_BLOCK;
   if (b0 >= total) return;
   // thread t owns the SCAN_ITEMS consecutive entries starting at b0 + t*SCAN_ITEMS
   uint32_t v[SCAN_ITEMS];
@@ -848,7 +871,7 @@ __global__ void __launch_bounds__(NT) k_scan_down(uint32_t* h, const uint32_t* p
     s += v[k];
   }
   uint32_t tot;
-  uint32_t run = block_excl_scan<NT>(s, sh, &tot) + part[blockIdx.x];
+  uint32_t run = block_excl_scan<NT>(s, sh, &tot) + part[bid];
   for (int k = 0; k < SCAN_ITEMS; k++) {
     uint64_t i = b0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
     if (i < total) h[i] = run;

@@ -84,6 +84,19 @@ constexpr int WIDE_CELLS = 1 << WIDE_CELL_BITS;
 __global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
   __shared__ uint32_t sk[WIDE_PMAX];
   const uint32_t p = w.p;
+  // tie entries and the trailing totals of both count arrays start at zero
+  // (the count kernel adds to them; it writes every other entry)
+  {
+    const uint32_t R = w.W + 2;
+    for (uint32_t b = threadIdx.x; b < p; b += NT) {
+      w.hf[(uint64_t)b * R] = 0;
+      w.hf[(uint64_t)b * R + R - 1] = 0;
+    }
+    if (threadIdx.x == 0) {
+      w.hf[(uint64_t)p * R] = 0;
+      w.ha[(uint64_t)WIDE_P1 * w.W] = 0;
+    }
+  }
   for (uint32_t r = threadIdx.x + 1; r < p; r += NT) {
     const uint32_t z = __builtin_ctz(r);
     const uint32_t k = (1u << (w.lgp - 1 - z)) + (r >> (z + 1));
@@ -162,20 +175,6 @@ __device__ __forceinline__ uint32_t wide_tie_bucket(const uint32_t* sk, const ui
   }
   kind = a > lo ? 1u : 2u;
   return a - 1;
-}
-
-// Tie entries and the trailing total of both count arrays start at zero
-// (the count kernel adds to them; it writes every other entry).
-__global__ void __launch_bounds__(256) k_wide_zero(WideArgs w) {
-  const uint32_t R = w.W + 2;
-  for (uint32_t b = blockIdx.x * 256 + threadIdx.x; b < w.p; b += gridDim.x * 256) {
-    w.hf[(uint64_t)b * R] = 0;
-    w.hf[(uint64_t)b * R + R - 1] = 0;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    w.hf[(uint64_t)w.p * R] = 0;
-    w.ha[(uint64_t)WIDE_P1 * w.W] = 0;
-  }
 }
 
 // keys of one chunk, issued ahead of their use (prefetch into registers)
