@@ -5,6 +5,7 @@
 #include "../../include/samplesort.h"
 #include "ss_kernels.h"
 #include "ss_wide.h"
+#include "ss_pairs.h"
 
 #include <hip/hip_runtime.h>
 
@@ -627,7 +628,13 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
       else LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 256>), dim3(tiles), dim3(NT), 0, st, a);
       LAUNCH_CHECK();
-      LAUNCH(PK_BUCKET_SORT, (k_bucket_sort<KW, VW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a, exp);
+      // stable slot sort; buckets too large or crowded go on to the radix /
+      // next-level kernel
+      LAUNCH(PK_BUCKET_SORT, (k_bucket_sort_pairs<KW, VW>), dim3((uint32_t)lv.bkt_cap), dim3(WIDE_BNT), 0, st, a,
+             exp);
+      LAUNCH_CHECK();
+      LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_pairs<KW, VW>), dim3((uint32_t)std::min<uint64_t>(lv.bkt_cap, 512)),
+             dim3(NT), 0, st, a);
     }
     LAUNCH_CHECK();
   }

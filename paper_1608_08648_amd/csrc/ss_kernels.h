@@ -57,7 +57,7 @@ template <int KW> struct SampleChunk {
 };
 
 // Keys per thread in one chunk of the stable split.
-template <int KW, int VW> struct SplitChunk {
+template <int KW, int VW, int PMAX = 256> struct SplitChunk {
   static constexpr int KS = (KW + VW <= 4) ? 8 : 4;
   static constexpr int CH = NT * KS;
 };
@@ -884,8 +884,8 @@ __global__ void __launch_bounds__(NT) k_scan_down(uint32_t* h, uint32_t* part, u
 template <int KW, int VW, int PMAX>
 struct ScatterLds {
   using KT = typename KeyOf<KW>::T;
-  static constexpr int KS = SplitChunk<KW, VW>::KS;
-  static constexpr int CH = SplitChunk<KW, VW>::CH;
+  static constexpr int KS = SplitChunk<KW, VW, PMAX>::KS;
+  static constexpr int CH = SplitChunk<KW, VW, PMAX>::CH;
   static constexpr int SLOTS = SortShape<NT, KS>::SLOTS;
   TreeLds<KW, PMAX> tr;
   uint32_t gofs[PMAX];   // next free in-segment position of each bucket

@@ -1,0 +1,233 @@
+// Stable bucket sort for (key, payload) pairs.
+//
+// The stable split (step 4) leaves every bucket in input order, so the
+// position of an element inside its bucket is its input order among equal
+// keys.  The slot sort of the keys-only path orders a bucket by counting its
+// keys into value slots and ranking each key inside its slot; here every
+// placed element also carries its position in the bucket, and the rank
+// inside a slot compares (key, position): equal keys keep input order, so
+// the result is the stable order (Section 1) without a radix pass per digit.
+#pragma once
+#include "ss_wide.h"
+
+namespace ss {
+
+// Elements per bucket in LDS (key, payload, 16-bit position): about 143 KB
+// next to the slot counters, for one 1024-thread work-group per CU.
+template <int KW, int VW> struct StableSlotCap {
+  static constexpr int C = (KW + VW <= 8) ? 14336 : ((KW + VW <= 12) ? 10240 : 7680);
+};
+constexpr uint32_t STABLE_MAX_FILL = 64;   // crowded-slot limit
+
+template <int KW, int VW>
+struct SlotStableLds {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  static constexpr int C = StableSlotCap<KW, VW>::C;
+  KT pk[C];
+  VT pv[C];
+  uint16_t pi[C];
+  uint32_t scnt[(1 << SLOT_LOG2) / 2];   // two 16-bit slot counters per word
+  alignas(8) uint64_t red[64];
+  uint32_t flag;
+};
+
+// Sorts in[0, len) (ord images) with payloads vin[0, len) into out / vout
+// (caller's key type), stable.  Returns false (having written nothing) when
+// the bucket is larger than the LDS or a slot is crowded.
+template <int KW, int VW, int NTH>
+__device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in, const typename ValOf<VW>::T* vin,
+                                                 typename KeyOf<KW>::T* out, typename ValOf<VW>::T* vout,
+                                                 uint32_t len, int kout, SlotStableLds<KW, VW>& sm, bool lo_known,
+                                                 typename KeyOf<KW>::T lo, bool hi_known,
+                                                 typename KeyOf<KW>::T hi) {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  constexpr int S = 1 << SLOT_LOG2;
+  constexpr int W = S / 2;
+  const int t = threadIdx.x;
+  if (len > (uint32_t)SlotStableLds<KW, VW>::C) return false;
+  KT mn = ~KT(0), mx = 0;
+  if (!(lo_known && hi_known)) {
+    for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
+      KT k[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        uint32_t i = i0 + u * NTH + t;
+        k[u] = i < len ? in[i] : KT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u++)
+        if (i0 + u * NTH + t < len) { mn = k[u] < mn ? k[u] : mn; mx = k[u] > mx ? k[u] : mx; }
+    }
+  }
+  for (int q = t; q < W; q += NTH) sm.scnt[q] = 0;
+  if (!(lo_known && hi_known)) block_minmax<NTH>(mn, mx, (KT*)sm.red);   // (ends with a barrier)
+  else __syncthreads();
+  if (lo_known) mn = lo;
+  if (hi_known) mx = hi;
+  if (mn == mx) {                          // one key value: the bucket is in input order already
+    for (uint32_t i = t; i < len; i += NTH) {
+      out[i] = from_ord(mn, kout);
+      vout[i] = vin[i];
+    }
+    return true;
+  }
+  const int bw = bit_width<KT>((KT)(mx - mn));
+  const int sh = bw > SLOT_LOG2 ? bw - SLOT_LOG2 : 0;
+  auto slot = [&](KT k) { return (uint32_t)((KT)(k - mn) >> sh); };
+  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
+    KT k[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      uint32_t i = i0 + u * NTH + t;
+      k[u] = i < len ? in[i] : KT(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      if (i0 + u * NTH + t < len) {
+        const uint32_t q = slot(k[u]);
+        atomicAdd(&sm.scnt[q >> 1], 1u << (16 * (q & 1)));
+      }
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the slot counts (16-bit halves), and the fullest slot
+  {
+    constexpr int PER = W / NTH;
+    uint32_t v[PER], sum = 0, mxc = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      v[j] = sm.scnt[t * PER + j];
+      const uint32_t a0 = v[j] & 0xFFFFu, a1 = v[j] >> 16;
+      sum += a0 + a1;
+      mxc = max(mxc, max(a0, a1));
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<NTH>(sum, (uint32_t*)sm.red, &tot);
+    const uint32_t wm = wave_max(mxc);
+    if (t == 0) sm.flag = 0;
+    __syncthreads();
+    if (lane_id() == 0 && wm > STABLE_MAX_FILL) atomicOr(&sm.flag, 1u);
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      const uint32_t a0 = v[j] & 0xFFFFu;
+      sm.scnt[t * PER + j] = run | ((run + a0) << 16);   // starts of slots 2w and 2w+1
+      run += a0 + (v[j] >> 16);
+    }
+  }
+  __syncthreads();
+  const bool crowded = sm.flag != 0;
+  __syncthreads();
+  if (crowded) return false;
+  // place (key, payload, position); afterwards each slot's counter holds its end
+  for (uint32_t i0 = 0; i0 < len; i0 += 4 * NTH) {
+    KT k[4];
+    VT v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint32_t i = i0 + u * NTH + t;
+      k[u] = i < len ? in[i] : KT(0);
+      v[u] = i < len ? vin[i] : VT(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint32_t i = i0 + u * NTH + t;
+      if (i < len) {
+        const uint32_t q = slot(k[u]);
+        const uint32_t sft = 16 * (q & 1);
+        const uint32_t pos = (atomicAdd(&sm.scnt[q >> 1], 1u << sft) >> sft) & 0xFFFFu;
+        sm.pk[pos] = k[u];
+        sm.pv[pos] = v[u];
+        sm.pi[pos] = (uint16_t)i;
+      }
+    }
+  }
+  __syncthreads();
+  // rank inside the slot by (key, position)
+  auto slot_end = [&](uint32_t q) { return (sm.scnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu; };
+  for (uint32_t j = t; j < len; j += NTH) {
+    const KT k = sm.pk[j];
+    const uint32_t ip = sm.pi[j];
+    const uint32_t q = slot(k);
+    const uint32_t s0 = q ? slot_end(q - 1) : 0u, s1 = slot_end(q);
+    uint32_t rank = 0;
+    for (uint32_t o = s0; o < s1; o++) {
+      const KT ko = sm.pk[o];
+      rank += (ko < k || (ko == k && sm.pi[o] < ip)) ? 1u : 0u;
+    }
+    out[s0 + rank] = from_ord(k, kout);
+    vout[s0 + rank] = sm.pv[j];
+  }
+  __syncthreads();
+  return true;
+}
+
+// Buckets of a split level (pairs): stable slot sort in LDS; buckets too
+// large or crowded go to the list of the radix / next-level kernel.
+template <int KW, int VW>
+__global__ void __launch_bounds__(WIDE_BNT) k_bucket_sort_pairs(LevelArgs a, int export_stages) {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  __shared__ SlotStableLds<KW, VW> sm;
+  const LevelCtl c = *a.ctl;
+  const uint32_t x = blockIdx.x;
+  if (x >= c.total_buckets) return;
+  const uint32_t si = find_seg(a.segs, c.nsegs, x, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
+  const SegDesc d = a.segs[si];
+  const uint32_t b = x - d.bkt_off;
+  const uint32_t base = a.hist[d.hist_off];
+  const uint32_t st = a.hist[d.hist_off + (uint64_t)b * d.ntiles] - base;
+  const uint32_t en = (b + 1 < d.p) ? a.hist[d.hist_off + (uint64_t)(b + 1) * d.ntiles] - base : d.len;
+  const uint32_t sz = en - st;
+  if (export_stages && d.depth == 0 && si == 0 && threadIdx.x == 0) a.exp_counts[b] = sz;
+  if (sz == 0) return;
+  const uint64_t gb = d.beg + st;
+  // the bucket's key range from its splitters (ranks b and b+1), when both exist
+  auto spl_key = [&](uint32_t r) -> KT {
+    const uint32_t z = __builtin_ctz(r);
+    const uint32_t k = (1u << (d.lgp - 1 - z)) + (r >> (z + 1));
+    const uint64_t node = ((const uint64_t*)a.tree)[d.tree_off + k];
+    if constexpr (KW == 4) return (KT)(node >> 32);
+    else return (KT)node;
+  };
+  const bool lo_k = b >= 1, hi_k = b + 1 < d.p;
+  const KT lo = lo_k ? spl_key(b) : KT(0);
+  const KT hi = hi_k ? spl_key(b + 1) : KT(0);
+  const bool done = slot_sort_stable<KW, VW, WIDE_BNT>((const KT*)a.dst + gb, (const VT*)a.vdst + gb,
+                                                        (KT*)a.out + gb, (VT*)a.vout + gb, sz, a.kout, sm, lo_k, lo,
+                                                        hi_k, hi);
+  if (threadIdx.x == 0) {
+    if (done) {
+      atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)sz);
+    } else {
+      const uint32_t k = atomicAdd(a.nleft, 1u);
+      a.left[k] = SmallEnt{gb, sz, x};
+    }
+  }
+}
+
+// Pairs: buckets handed on -- stable radix sort in LDS, or the next level /
+// fallback when larger than one work-group.
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_bucket_leftover_pairs(LevelArgs a) {
+  using KT = typename KeyOf<KW>::T;
+  constexpr uint32_t C = SmallCap<KW, VW>::C;
+  __shared__ SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> sm;
+  const uint32_t nl = *a.nleft;
+  for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+    const SmallEnt e = a.left[li];
+    if (e.len <= C) {
+      sort_small<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, e.beg, e.len, 0, 0, a.kout, sm);
+      if (threadIdx.x == 0) atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)e.len);
+      continue;
+    }
+    const LevelCtl c = *a.ctl;
+    const uint32_t si = find_seg(a.segs, c.nsegs, e.pad, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
+    const SegDesc d = a.segs[si];
+    bucket_overflow<KW, VW>(a, d, e.pad - d.bkt_off, e.beg, e.len, sm);
+    __syncthreads();
+  }
+}
+
+}  // namespace ss
