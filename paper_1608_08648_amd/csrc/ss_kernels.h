@@ -10,9 +10,10 @@
 //   k_classify      count, per tile, the keys of each bucket (step 4)
 //   k_scan_*        exclusive scan of the bucket-major counts -> offsets
 //   k_scatter       stable split of the keys into their buckets (step 4)
-//   k_bucket_sort   sort every bucket in LDS; buckets too large for one
-//                   work-group go to the next level's list (or, past the
-//                   last planned level, to a one-work-group merge sort)
+//   k_bucket_sort_* sort every bucket in LDS (slot sorts; ss_pairs.h for
+//                   pairs); buckets too large for one work-group go to the
+//                   next level's list (or, past the last planned level, to
+//                   a one-work-group merge sort)
 // Keys are compared through their order-preserving unsigned image (ord);
 // ties are broken by the index inside the segment (Section 2.2's tags), so
 // every key is distinct for the split and the result is the stable order.
@@ -1014,34 +1015,6 @@ __device__ __forceinline__ void bucket_overflow(const LevelArgs& a, const SegDes
   sort_big_wg<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, alt, valt, gb, sz, 0, 0, a.kout, sm);
 }
 
-// Buckets of the level: sort in LDS, or hand to the next level / fallback.
-template <int KW, int VW>
-__global__ void __launch_bounds__(NT) k_bucket_sort(LevelArgs a, int export_stages) {
-  using KT = typename KeyOf<KW>::T;
-  constexpr int KMAX = SmallCap<KW, VW>::KMAX;
-  constexpr uint32_t C = SmallCap<KW, VW>::C;
-  __shared__ SmallLds<KW, VW, KMAX> sm;
-  const LevelCtl c = *a.ctl;
-  const uint32_t x = blockIdx.x;
-  if (x >= c.total_buckets) return;
-  const uint32_t si = find_seg(a.segs, c.nsegs, x, [](const SegDesc& d) { return (uint64_t)d.bkt_off; });
-  const SegDesc d = a.segs[si];
-  const uint32_t b = x - d.bkt_off;
-  const uint32_t base = a.hist[d.hist_off];
-  const uint32_t st = a.hist[d.hist_off + (uint64_t)b * d.ntiles] - base;
-  const uint32_t en = (b + 1 < d.p) ? a.hist[d.hist_off + (uint64_t)(b + 1) * d.ntiles] - base : d.len;
-  const uint32_t sz = en - st;
-  if (export_stages && d.depth == 0 && si == 0 && threadIdx.x == 0) a.exp_counts[b] = sz;
-  if (sz == 0) return;
-  const uint64_t gb = d.beg + st;
-  if (sz <= C) {
-    sort_small<KW, VW>((const KT*)a.dst, a.vdst, (KT*)a.out, a.vout, gb, sz, 0, 0, a.kout, sm);
-    if (threadIdx.x == 0) atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)sz);
-    return;
-  }
-  bucket_overflow<KW, VW>(a, d, b, gb, sz, sm);
-}
-
 // ------------------------------------------- keys-only (unstable) paths
 //
 // With no payload, keys that compare equal have identical bits, so the
@@ -1061,9 +1034,9 @@ struct ScatterKeysLds {
   using BT = typename std::conditional<(PMAX <= 256), uint8_t, uint16_t>::type;
   static constexpr int CH = SplitU<KW, PMAX>::CH;
   TreeLds<KW, PMAX> tr;
-  uint32_t gofs[PMAX];      // in-segment position of each bucket's run for the current chunk
+  uint32_t gofs[PMAX];      // before the first chunk: in-segment position of each bucket's run;
+                            // then that position - chunk position of the current chunk's run
   uint32_t cur[2][PMAX];    // chunk counts, then cursors (alternating chunks)
-  uint32_t cst[2][PMAX];    // chunk start of each bucket (alternating chunks)
   KT sk[CH];                // chunk keys grouped by bucket
   BT sb[CH];                // their buckets
   alignas(8) uint32_t red[32];
@@ -1112,7 +1085,7 @@ __device__ __forceinline__ void split_chunk(const LevelArgs& a, const SegDesc& d
       v[j] = 0;
       if (bb < d.p) {
         if (!first) {
-          sm.gofs[bb] += sm.cur[o][bb] - sm.cst[o][bb];
+          sm.gofs[bb] += sm.cur[o][bb];    // (previous delta + previous chunk's end of the run)
           sm.cur[o][bb] = 0;
         }
         v[j] = sm.cur[x][bb];
@@ -1124,7 +1097,7 @@ __device__ __forceinline__ void split_chunk(const LevelArgs& a, const SegDesc& d
 #pragma unroll
     for (int j = 0; j < PER; j++) {
       uint32_t bb = t * PER + j;
-      if (bb < d.p) { sm.cst[x][bb] = run; sm.cur[x][bb] = run; }
+      if (bb < d.p) { sm.cur[x][bb] = run; sm.gofs[bb] -= run; }
       run += v[j];
     }
   }
@@ -1151,10 +1124,7 @@ __device__ __forceinline__ void split_chunk(const LevelArgs& a, const SegDesc& d
   __syncthreads();
   const uint32_t lim = FULL ? (uint32_t)CH : cn;
 #pragma unroll 4
-  for (uint32_t j = t; j < lim; j += NT) {
-    uint32_t bb = sm.sb[j];
-    dst[sm.gofs[bb] + (j - sm.cst[x][bb])] = sm.sk[j];
-  }
+  for (uint32_t j = t; j < lim; j += NT) dst[sm.gofs[sm.sb[j]] + j] = sm.sk[j];
 }
 
 template <int KW, int PMAX>

@@ -299,9 +299,9 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
 // shared by both passes (NB buckets; bucket ~0u = key not moved).
 template <int NB>
 struct WideSplitLds {
-  uint32_t gofs[NB];       // output position of each bucket's run for the current chunk
+  uint32_t gofs[NB];       // before the first chunk: output position of each bucket's run;
+                           // then output position - chunk position of the current chunk's run
   uint32_t cur[2][NB];     // chunk counts, then cursors (alternating chunks)
-  uint32_t cst[2][NB];     // chunk start of each bucket (alternating chunks)
   uint32_t ctot[2];        // keys of the chunk that move
   uint32_t sk[WIDE_CH];
   uint8_t sb[WIDE_CH];
@@ -329,14 +329,15 @@ __device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uin
   // (NB <= 64: one wave)
   if (t < NB) {
     const int o = x ^ 1;
+    uint32_t g = sm.gofs[t];               // output position of the bucket's next run
     if (!first) {
-      sm.gofs[t] += sm.cur[o][t] - sm.cst[o][t];
+      g += sm.cur[o][t];                   // (previous delta + previous chunk's end of the run)
       sm.cur[o][t] = 0;
     }
     const uint32_t v = sm.cur[x][t];
     const uint32_t inc = wave_incl_scan(v);
-    sm.cst[x][t] = inc - v;
     sm.cur[x][t] = inc - v;
+    sm.gofs[t] = g - (inc - v);
     if (t == NB - 1) sm.ctot[x] = inc;
   }
   __syncthreads();
@@ -362,10 +363,7 @@ __device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uin
   __syncthreads();
   const uint32_t tot = sm.ctot[x];
 #pragma unroll 4
-  for (uint32_t j = t; j < tot; j += NT) {
-    const uint32_t bb = sm.sb[j];
-    dst[sm.gofs[bb] + (j - sm.cst[x][bb])] = sm.sk[j];
-  }
+  for (uint32_t j = t; j < tot; j += NT) dst[sm.gofs[sm.sb[j]] + j] = sm.sk[j];
 }
 
 struct WideALds {
