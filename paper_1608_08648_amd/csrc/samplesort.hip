@@ -626,7 +626,7 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<KW>), dim3(gl), dim3(NT), 0, st, a, KW == 4 ? 1 : 0);
     } else {
       if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
-      else LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 256>), dim3(tiles), dim3(NT), 0, st, a);
+      else LAUNCH(PK_SCATTER, (k_scatter_pairs<KW, VW>), dim3(tiles), dim3(NT), 0, st, a);
       LAUNCH_CHECK();
       // stable slot sort; buckets too large or crowded go on to the radix /
       // next-level kernel

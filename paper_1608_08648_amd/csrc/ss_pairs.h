@@ -230,4 +230,159 @@ __global__ void __launch_bounds__(NT) k_bucket_leftover_pairs(LevelArgs a) {
   }
 }
 
+// ---------------------------------------------------- stable split
+
+// Stable split (step 4) of pairs into at most 256 buckets without a sort of
+// the chunk: wave w takes the contiguous keys [w*R*64, (w+1)*R*64) of the
+// chunk as R rows of 64.  Inside a row, the lanes with the same bucket are
+// found with one ballot per bucket bit, so a key's rank among them is the
+// number of such lanes before it; a per-wave counter per bucket, advanced
+// row by row, adds the earlier rows.  The waves' counts then give each
+// wave's offset inside each bucket's run, so every key's position follows
+// input order (stability); the chunk is grouped by bucket in LDS and every
+// bucket's run is written contiguously.
+constexpr int PAIRS_R = 8;                   // rows per wave in a chunk
+constexpr int PAIRS_CH = PAIRS_R * NT;       // keys per chunk
+constexpr int PAIRS_WAVES = NT / WAVE;
+
+template <int KW, int VW>
+struct ScatterPairsLds {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  TreeLds<KW, 256> tr;
+  uint32_t wcnt[PAIRS_WAVES][256];           // per-wave running counts, then the waves' offsets
+  uint32_t gofs[256];                        // before the first chunk: in-segment position of each
+                                             // bucket's run; then that position - chunk position
+  uint32_t tot[256];                         // keys of each bucket in the chunk
+  KT sk[PAIRS_CH];
+  VT sv[PAIRS_CH];
+  uint8_t sb[PAIRS_CH];
+  alignas(8) uint32_t red[32];
+};
+
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_scatter_pairs(LevelArgs a) {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  constexpr int R = PAIRS_R;
+  __shared__ ScatterPairsLds<KW, VW> sm;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const LevelCtl c = *a.ctl;
+  if (tile >= c.total_tiles) return;
+  const uint32_t si = find_seg(a.segs, c.nsegs, tile, [](const SegDesc& d) { return (uint64_t)d.tile_off; });
+  const SegDesc d = a.segs[si];
+  const uint32_t tw = tile - d.tile_off;
+  const int t = threadIdx.x, w = wave_id(), ln = lane_id();
+  sm.tr.load(a.tree, a.tree_tag, d.tree_off, d.p);
+  const uint32_t base = a.hist[d.hist_off];
+  for (uint32_t b = t; b < 256; b += NT) {
+    sm.gofs[b] = b < d.p ? a.hist[d.hist_off + (uint64_t)b * d.ntiles + tw] - base : 0u;
+    for (int v = 0; v < PAIRS_WAVES; v++) sm.wcnt[v][b] = 0;
+  }
+  __syncthreads();
+  const uint32_t t0 = tw * a.tile;
+  const uint32_t t1 = min(t0 + a.tile, d.len);
+  const KT* src = (const KT*)a.src + d.beg;
+  const VT* vsrc = (const VT*)a.vsrc;
+  KT* dst = (KT*)a.dst + d.beg;
+  VT* vdst = (VT*)a.vdst + d.beg;
+  const uint32_t nbits = d.lgp + 1;          // bucket p marks keys past the end of the tile
+  for (uint32_t c0 = t0; c0 < t1; c0 += PAIRS_CH) {
+    const uint32_t cn = min((uint32_t)PAIRS_CH, t1 - c0);
+    KT key[R];
+    VT val[R];
+    uint32_t tag[R], bk[R], off[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const uint32_t i = (uint32_t)(w * R + r) * WAVE + ln;   // chunk position: wave, row, lane
+      tag[r] = c0 + i;
+      key[r] = 0;
+      val[r] = 0;
+      if (i < cn) {
+        key[r] = to_ord(src[c0 + i], a.kin);
+        val[r] = a.iota ? (VT)(c0 + i) : vsrc[d.beg + c0 + i];
+      }
+    }
+    sm.tr.template classify_many<R>(key, tag, d.lgp, d.p, bk);
+    // rank among the lanes of the row with the same bucket, plus the wave's
+    // earlier rows of that bucket
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const uint32_t i = (uint32_t)(w * R + r) * WAVE + ln;
+      const uint32_t b = i < cn ? bk[r] : d.p;
+      uint64_t peers = ~0ull;
+      for (uint32_t bit = 0; bit < nbits; bit++) {
+        const bool on = (b >> bit) & 1u;
+        const uint64_t m = __ballot(on);
+        peers &= on ? m : ~m;
+      }
+      const uint32_t rank = lane_rank(peers);
+      uint32_t o = 0;
+      if (b < d.p) {
+        o = sm.wcnt[w][b];
+        if (rank == 0) sm.wcnt[w][b] = o + (uint32_t)__popcll(peers);
+      }
+      off[r] = o + rank;
+      bk[r] = b;
+    }
+    __syncthreads();
+    // per bucket: the waves' offsets, the chunk total, then chunk starts
+    {
+      constexpr int PER = (256 + NT - 1) / NT;
+      uint32_t v[PER], sum = 0;
+#pragma unroll
+      for (int j = 0; j < PER; j++) {
+        const uint32_t b = t * PER + j;
+        uint32_t run = 0;
+        if (b < 256) {
+          for (int ww = 0; ww < PAIRS_WAVES; ww++) {
+            const uint32_t x = sm.wcnt[ww][b];
+            sm.wcnt[ww][b] = run;
+            run += x;
+          }
+        }
+        v[j] = run;
+        sum += run;
+      }
+      uint32_t total;
+      uint32_t cs = block_excl_scan<NT>(sum, sm.red, &total);
+#pragma unroll
+      for (int j = 0; j < PER; j++) {
+        const uint32_t b = t * PER + j;
+        if (b < 256) {
+          sm.tot[b] = cs;                    // chunk start of the bucket
+          sm.gofs[b] -= cs;                  // output position - chunk position
+        }
+        cs += v[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const uint32_t b = bk[r];
+      if (b < d.p) {
+        const uint32_t pos = sm.tot[b] + sm.wcnt[w][b] + off[r];
+        sm.sk[pos] = key[r];
+        sm.sv[pos] = val[r];
+        sm.sb[pos] = (uint8_t)b;
+      }
+    }
+    __syncthreads();
+    for (uint32_t j = t; j < cn; j += NT) {
+      const uint32_t g = sm.gofs[sm.sb[j]] + j;
+      dst[g] = sm.sk[j];
+      vdst[g] = sm.sv[j];
+    }
+    __syncthreads();
+    // next chunk: each bucket's run continues after this chunk's keys
+    // (chunk start + total = next bucket's chunk start), counters from zero
+    for (uint32_t b = t; b < 256; b += NT) {
+      const uint32_t nx = (b + 1 < 256) ? sm.tot[b + 1] : cn;
+      sm.gofs[b] += nx;
+      for (int v = 0; v < PAIRS_WAVES; v++) sm.wcnt[v][b] = 0;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace ss
