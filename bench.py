@@ -2,11 +2,12 @@
 """Benchmark of the MI355X sample sort.
 
 Default workload: 2^26 int32 keys (uniform, seeded, synthetic), keys only,
-random oversampling with p = 256 buckets and oversampling s = 16, resident
-in HBM before the timed region.  One step = one full sort: per split level
-sample, sample sort, splitters, classify, scan and scatter, then the bucket
-sorts (with p = 256 each top bucket of ~2^18 keys is split once more, by the
-next level, before the bucket sorts).
+random oversampling with p = 4096 buckets and oversampling s = 16, resident
+in HBM before the timed region.  One step = one full sort: sample, sample
+sort, splitters, classification and counts, scans, the split (for p >= 1024
+in two passes: 64 coarse regions, then the fine buckets) and the bucket
+sorts.  With p < 1024 a top bucket too large for one work-group is split
+once more by the next level before the bucket sorts.
 
 Prints ONE JSON line with Gkeys/s, the roofline of the dominant kernel
 (algorithmic bytes / its HIP-event time, against 8 TB/s HBM) and the CPU
@@ -49,7 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sort", choices=["sort", "pairs", "segmented", "autograd"])
     ap.add_argument("--log2n", type=int, default=26)
-    ap.add_argument("--p", type=int, default=256)
+    ap.add_argument("--p", type=int, default=4096)
     ap.add_argument("--s", type=int, default=16)
     ap.add_argument("--sampling", default="random", choices=["random", "regular"])
     ap.add_argument("--dist", default="uniform")

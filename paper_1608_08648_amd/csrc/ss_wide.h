@@ -44,6 +44,7 @@ constexpr uint32_t WIDE_P1 = 1u << WIDE_LG1;   // coarse buckets
 constexpr int WIDE_PMAX = 4096;
 constexpr int WIDE_U = 16;                     // keys per thread per chunk
 constexpr int WIDE_CH = WIDE_U * NT;
+constexpr int WIDE_UA = 8;                     // keys per thread per chunk of the first pass (LDS)
 constexpr uint32_t WIDE_TILE = 7 * WIDE_U * 512; // keys per input tile (< 2^16: 16-bit tie counters)
 constexpr uint32_t WIDE_TB = 65536;            // nominal keys per piece of the second pass
 // bucket sort of the wide split: 1024 threads, 30720 keys per round in LDS
@@ -178,14 +179,15 @@ __device__ __forceinline__ uint32_t wide_tie_bucket(const uint32_t* sk, const ui
 }
 
 // keys of one chunk, issued ahead of their use (prefetch into registers)
-__device__ __forceinline__ void wide_load(uint32_t (&k)[WIDE_U], const uint32_t* src, uint32_t i0, uint32_t end) {
+template <int U>
+__device__ __forceinline__ void wide_load(uint32_t (&k)[U], const uint32_t* src, uint32_t i0, uint32_t end) {
   const int t = threadIdx.x;
-  if (i0 + WIDE_CH <= end) {
+  if (i0 + U * NT <= end) {
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) k[u] = src[i0 + u * NT + t];
+    for (int u = 0; u < U; u++) k[u] = src[i0 + u * NT + t];
   } else {
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) {
+    for (int u = 0; u < U; u++) {
       const uint32_t i = i0 + u * NT + t;
       k[u] = i < end ? src[i] : 0u;
     }
@@ -297,19 +299,19 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
 
 // Grouping of one chunk by bucket in LDS, then contiguous run writes:
 // shared by both passes (NB buckets; bucket ~0u = key not moved).
-template <int NB>
+template <int NB, int U = WIDE_U>
 struct WideSplitLds {
   uint32_t gofs[NB];       // before the first chunk: output position of each bucket's run;
                            // then output position - chunk position of the current chunk's run
   uint32_t cur[2][NB];     // chunk counts, then cursors (alternating chunks)
   uint32_t ctot[2];        // keys of the chunk that move
-  uint32_t sk[WIDE_CH];
-  uint8_t sb[WIDE_CH];
+  uint32_t sk[U * NT];
+  uint8_t sb[U * NT];
 };
 
-template <int NB>
-__device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uint32_t (&key)[WIDE_U],
-                                                 const uint32_t (&bk)[WIDE_U], uint32_t* dst, int x, bool first) {
+template <int NB, int U>
+__device__ __forceinline__ void wide_group_write(WideSplitLds<NB, U>& sm, const uint32_t (&key)[U],
+                                                 const uint32_t (&bk)[U], uint32_t* dst, int x, bool first) {
   const int t = threadIdx.x;
   // sorted or constant input puts a wave's row of 64 keys into one bucket:
   // then (tested on the first row) each row claims its slots with one
@@ -317,11 +319,11 @@ __device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uin
   const bool rows = __ballot(bk[0] == __builtin_amdgcn_readfirstlane(bk[0])) == __ballot(1);
   if (rows) {
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++)
+    for (int u = 0; u < U; u++)
       if (bk[u] != ~0u) lds_count(sm.cur[x], bk[u]);
   } else {
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++)
+    for (int u = 0; u < U; u++)
       if (bk[u] != ~0u) atomicAdd(&sm.cur[x][bk[u]], 1u);
   }
   __syncthreads();
@@ -343,7 +345,7 @@ __device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uin
   __syncthreads();
   if (rows) {
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) {
+    for (int u = 0; u < U; u++) {
       if (bk[u] != ~0u) {
         const uint32_t pos = lds_claim(sm.cur[x], bk[u]);
         sm.sk[pos] = key[u];
@@ -352,7 +354,7 @@ __device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uin
     }
   } else {
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) {
+    for (int u = 0; u < U; u++) {
       if (bk[u] != ~0u) {
         const uint32_t pos = atomicAdd(&sm.cur[x][bk[u]], 1u);
         sm.sk[pos] = key[u];
@@ -369,7 +371,7 @@ __device__ __forceinline__ void wide_group_write(WideSplitLds<NB>& sm, const uin
 struct WideALds {
   uint32_t sk[WIDE_PMAX];
   uint32_t cells[WIDE_CELLS];
-  WideSplitLds<WIDE_P1> g;
+  WideSplitLds<WIDE_P1, WIDE_UA> g;
 };
 
 // First pass, per input tile: non-tie keys to their coarse region, in runs.
@@ -383,7 +385,7 @@ __global__ void __launch_bounds__(NT) k_wide_split_a(WideArgs w) {
   const uint32_t p = w.p, lg2 = w.lgp - WIDE_LG1;
   const uint32_t t0 = tile * w.tile, t1 = min(t0 + w.tile, w.n);
   const uint32_t* src = (const uint32_t*)w.src;
-  uint32_t nk[WIDE_U];
+  uint32_t nk[WIDE_UA];
   wide_load(nk, src, t0, t1);
   for (uint32_t k = t; k < p; k += NT) sm.sk[k] = w.skeys[k];
   const WideHdr h = *w.hdr;
@@ -395,25 +397,25 @@ __global__ void __launch_bounds__(NT) k_wide_split_a(WideArgs w) {
   }
   __syncthreads();
   int x = 0;
-  for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_CH, x ^= 1) {
-    uint32_t key[WIDE_U], c[WIDE_U];
+  for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_UA * NT, x ^= 1) {
+    uint32_t key[WIDE_UA], c[WIDE_UA];
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) key[u] = to_ord(nk[u], w.kin);
-    if (i0 + WIDE_CH < t1) wide_load(nk, src, i0 + WIDE_CH, t1);
+    for (int u = 0; u < WIDE_UA; u++) key[u] = to_ord(nk[u], w.kin);
+    if (i0 + WIDE_UA * NT < t1) wide_load(nk, src, i0 + WIDE_UA * NT, t1);
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) {
+    for (int u = 0; u < WIDE_UA; u++) {
       bool tie;
       const uint32_t lo = wide_lower(sm.sk, sm.cells, h, p, key[u], tie);
       c[u] = (i0 + u * NT + t < t1 && !tie) ? ((lo - 1) >> lg2) : ~0u;
     }
-    wide_group_write<WIDE_P1>(sm.g, key, c, w.stage, x, i0 == t0);
+    wide_group_write(sm.g, key, c, w.stage, x, i0 == t0);
   }
 }
 
 struct WideBLds {
   uint32_t sub[64];        // the coarse bucket's subtree (keys), local Eytzinger slots [1, P2)
   uint32_t info[4];
-  WideSplitLds<64> g;
+  WideSplitLds<64, WIDE_UA> g;
 };
 
 // Second pass.  Coarse region c is cut into pieces at input-tile
@@ -463,7 +465,7 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
   if (wl >= wh) return;                           // no run starts here (uniform across the group)
   const uint32_t r0 = w.ha[(uint64_t)c * W + wl];
   const uint32_t r1 = (wh < W) ? w.ha[(uint64_t)c * W + wh] : re;
-  uint32_t nk[WIDE_U];
+  uint32_t nk[WIDE_UA];
   wide_load(nk, w.stage, r0, r1);
   const uint32_t R = W + 2;
   if (t < 64) {                                   // P2 <= 64 fine buckets; the rest stay empty
@@ -479,21 +481,21 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
   }
   __syncthreads();
   int x = 0;
-  for (uint32_t i0 = r0; i0 < r1; i0 += WIDE_CH, x ^= 1) {
-    uint32_t key[WIDE_U], f[WIDE_U];
+  for (uint32_t i0 = r0; i0 < r1; i0 += WIDE_UA * NT, x ^= 1) {
+    uint32_t key[WIDE_UA], f[WIDE_UA];
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) {
+    for (int u = 0; u < WIDE_UA; u++) {
       key[u] = nk[u];
       f[u] = 1;
     }
-    if (i0 + WIDE_CH < r1) wide_load(nk, w.stage, i0 + WIDE_CH, r1);
+    if (i0 + WIDE_UA * NT < r1) wide_load(nk, w.stage, i0 + WIDE_UA * NT, r1);
     for (uint32_t l = 0; l < lg2; l++) {
 #pragma unroll
-      for (int u = 0; u < WIDE_U; u++) f[u] = 2 * f[u] + (sm.sub[f[u]] < key[u] ? 1u : 0u);
+      for (int u = 0; u < WIDE_UA; u++) f[u] = 2 * f[u] + (sm.sub[f[u]] < key[u] ? 1u : 0u);
     }
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) f[u] = (i0 + u * NT + t < r1) ? f[u] - P2 : ~0u;
-    wide_group_write<64>(sm.g, key, f, w.fine, x, i0 == r0);
+    for (int u = 0; u < WIDE_UA; u++) f[u] = (i0 + u * NT + t < r1) ? f[u] - P2 : ~0u;
+    wide_group_write(sm.g, key, f, w.fine, x, i0 == r0);
   }
 }
 
