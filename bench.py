@@ -36,9 +36,9 @@ HBM_PEAK_GBS = 8000.0
 # KiB).  Valid only for the kernel sources and the workload they were taken
 # on; "traffic" is null for anything else.
 MEASURED_TRAFFIC = {
-    ("scatter", 26, 256, 16, "random", "uniform"): {
-        "src_sha256_16": "7bd8bef4e7af2614",
-        "bytes_per_launch": 582643917,   # mean of the two levels' launches: 596,475 and 541,501 KiB
+    ("bucket_sort", 26, 4096, 16, "random", "uniform"): {
+        "src_sha256_16": "52f8c40eba344f3e",
+        "bytes_per_launch": 547009894,   # k_wide_bucket: FETCH 135,848 KiB x 2 + WRITE 262,494 KiB
     },
 }
 
