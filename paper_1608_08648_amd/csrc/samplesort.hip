@@ -178,7 +178,7 @@ struct LevelsPlan {
 // device (p0 == 0).  N = total elements, maxlen0 = longest top segment.
 void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint64_t maxlen0, uint32_t p0,
                  uint64_t m0, uint64_t est_max0, uint32_t s, uint32_t p_cap, uint32_t tile_req, bool recurse,
-                 LevelsPlan* P) {
+                 LevelsPlan* P, uint32_t cpush0 = 0) {
   const uint32_t C = small_cap(ty.KW, ty.VW);
   // buckets larger than this go one level down when there is a level below
   // (keys only: beyond the slot sort's capacity)
@@ -240,7 +240,8 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
     // the top level of a single sort has a caller-chosen p, so its buckets
     // may well exceed the slot sort; deeper levels pick p for the target
     // size, and only a rare tail exceeds it: those take the radix sort
-    if (!recurse || est <= ((l == 0 && p0) ? Cpush : C)) break;
+    // (cpush0: the top level's own bucket sort capacity, when it has one)
+    if (!recurse || est <= ((l == 0 && p0) ? (cpush0 ? cpush0 : Cpush) : C)) break;
   }
 }
 
@@ -268,6 +269,7 @@ struct Plan {
   bool wide = false;
   uint32_t wide_W = 0;
   size_t o_whf = 0, o_whf_part = 0, o_wha = 0, o_wha_part = 0, o_wkeys = 0, o_wtags = 0, o_wcells = 0, o_whdr = 0;
+  size_t o_tmp2 = 0;       // wide split with a level below and input == output: first-pass buffer
   size_t bytes = 0;
   ~Plan() { delete nested; }
 };
@@ -337,11 +339,10 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   P->o_tmp = L.take((size_t)ty.KW * n);
   P->o_vtmp = ty.VW ? L.take((size_t)ty.VW * n) : 0;
   bool recurse = !(prm.flags & SS_F_NO_RECURSION);
-  // wide split: many buckets of keys only, each small enough for the round-based slot sort
-  P->wide = ty.VW == 0 && ty.KW == 4 && p >= 1024 && p <= (uint32_t)WIDE_PMAX && !(prm.flags & SS_F_NO_WIDE) &&
-            (double)n / p * spread(prm.s) < 65536.0;
+  // wide split: many buckets of keys only; buckets beyond the round-based
+  // slot sort's 65535 keys go one level down
+  P->wide = ty.VW == 0 && ty.KW == 4 && p >= 1024 && p <= (uint32_t)WIDE_PMAX && !(prm.flags & SS_F_NO_WIDE);
   if (P->wide) {
-    recurse = false;
     const uint64_t W = cdiv(n, WIDE_TILE);
     P->wide_W = (uint32_t)W;
     const uint64_t nf = (uint64_t)p * (W + 2) + 1, na = (uint64_t)WIDE_P1 * W + 1;
@@ -354,7 +355,12 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
     P->o_wcells = L.take(4 * (size_t)WIDE_CELLS);
     P->o_whdr = L.take(sizeof(WideHdr));
   }
-  plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp);
+  // (the wide split's bucket sort takes any size in rounds; a level below
+  // pays once buckets would need many rounds)
+  plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp, P->wide ? 2 * WIDE_BMAX : 0);
+  // the wide split's buckets must end up in tmp when a level below reads
+  // them; with input == output its first pass then needs a buffer of its own
+  if (P->wide && P->lp.nlev > 1) P->o_tmp2 = L.take((size_t)ty.KW * n);
   if (P->regular) {
     // blocks sorted with their in-block index as payload (Alg. 1 step 1)
     P->o_regk = L.take((size_t)ty.KW * n);
@@ -492,8 +498,10 @@ uint32_t grid_of(uint64_t work, uint32_t per, uint32_t cap) {
 
 // The wide split of a single keys-only sort (level 0 after its splitter
 // tree): count, scans, two split passes, bucket sorts.  The keys travel
-// input -> stage -> fine -> output; with input == output the stage is the
-// workspace copy and the bucket sort works in place.
+// input -> stage -> fine -> output.  Without a level below, input == output
+// puts the stage in the workspace copy and sorts the buckets in place; with
+// a level below, the fine buckets are always in the workspace copy (where
+// that level reads them).
 int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, int exp, hipStream_t st) {
   WideArgs w{};
   const bool inplace = in == out;
@@ -502,8 +510,14 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   w.hf = (uint32_t*)(ws + P.o_whf);
   w.ha = (uint32_t*)(ws + P.o_wha);
   w.src = in;
-  w.stage = inplace ? tmp : (uint32_t*)out;
-  w.fine = inplace ? (uint32_t*)out : tmp;
+  if (P.lp.nlev > 1) {
+    // the level below reads the fine buckets from tmp
+    w.stage = inplace ? (uint32_t*)(ws + P.o_tmp2) : (uint32_t*)out;
+    w.fine = tmp;
+  } else {
+    w.stage = inplace ? tmp : (uint32_t*)out;
+    w.fine = inplace ? (uint32_t*)out : tmp;
+  }
   w.out = out;
   w.n = (uint32_t)P.n;
   w.p = P.p_eff;

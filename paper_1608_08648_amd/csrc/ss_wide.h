@@ -51,6 +51,7 @@ constexpr uint32_t WIDE_TB = 65536;            // nominal keys per piece of the 
 // (one work-group per CU), buckets of up to 65535 keys
 constexpr int WIDE_BNT = 1024;
 constexpr int WIDE_BCAP = 30720;
+constexpr uint32_t WIDE_BMAX = 65535;          // largest bucket the round-based slot sort takes
 
 struct WideHdr { uint32_t kmin, kmax, sh, ncell; };
 
@@ -508,6 +509,7 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
 // (from L2).  Returns false (having written nothing) when a slot is too
 // crowded or the bucket too large.
 constexpr int ROUNDS_LOG2 = 14;   // S = 16384 slots: about one key per slot for 16K-key buckets
+constexpr uint32_t ROUNDS_MAX = 64;     // rounds the LDS bookkeeping has room for
 
 template <int CAP>
 struct SlotRoundsLds {
@@ -515,22 +517,27 @@ struct SlotRoundsLds {
   uint32_t cnt[(1 << ROUNDS_LOG2) / 2];   // 16-bit slot counts, then starts, then cursors / ends, two per word
   alignas(8) uint64_t red[64];
   uint32_t flag;
-  uint32_t rslot[8], rbase[8];    // first slot and first position of each round
+  uint32_t rslot[ROUNDS_MAX + 1], rbase[ROUNDS_MAX + 1];   // first slot and first position of each round
 };
 
 // (crowded: a slot of more than ROUNDS_MAX_FILL keys, whose ranking would
 // cost that many steps per key)
 constexpr uint32_t ROUNDS_MAX_FILL = 256;
 
-template <int NTH, int CAP>
+// C16: 16-bit counters over 2^ROUNDS_LOG2 slots (buckets up to 65535 keys);
+// otherwise 32-bit counters over half as many slots in the same LDS
+// (buckets of any size, in more rounds).
+template <int NTH, int CAP, bool C16 = true>
 __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* out, uint32_t len, int kout,
                                                  SlotRoundsLds<CAP>& sm, bool lo_known, uint32_t lo, bool hi_known,
                                                  uint32_t hi) {
-  constexpr int S = 1 << ROUNDS_LOG2;
-  constexpr int W = S / 2;
+  constexpr int LG = C16 ? ROUNDS_LOG2 : ROUNDS_LOG2 - 1;
+  constexpr int S = 1 << LG;
+  constexpr int W = C16 ? S / 2 : S;       // counter words
   constexpr uint32_t CR = CAP - ROUNDS_MAX_FILL;
   const int t = threadIdx.x;
-  if (len > 65535u) return false;          // (16-bit counters and positions)
+  if (C16 && len > 65535u) return false;   // (16-bit counters and positions)
+  if ((len + (CAP - ROUNDS_MAX_FILL) - 1) / (CAP - ROUNDS_MAX_FILL) > ROUNDS_MAX) return false;
   uint32_t mn = ~0u, mx = 0;
   if (!(lo_known && hi_known)) {
     for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
@@ -555,9 +562,21 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
     return true;
   }
   const int bw = bit_width<uint32_t>(mx - mn);
-  const int sh = bw > ROUNDS_LOG2 ? bw - ROUNDS_LOG2 : 0;
+  const int sh = bw > LG ? bw - LG : 0;
   auto slot = [&](uint32_t k) { return (k - mn) >> sh; };
-  auto get = [&](uint32_t q) { return (sm.cnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu; };
+  auto get = [&](uint32_t q) {
+    if constexpr (C16) return (sm.cnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+    else return sm.cnt[q];
+  };
+  // old value of slot q's counter, then += 1
+  auto inc = [&](uint32_t q) -> uint32_t {
+    if constexpr (C16) {
+      const uint32_t sft = 16 * (q & 1);
+      return (atomicAdd(&sm.cnt[q >> 1], 1u << sft) >> sft) & 0xFFFFu;
+    } else {
+      return atomicAdd(&sm.cnt[q], 1u);
+    }
+  };
   for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
     uint32_t k[8];
 #pragma unroll
@@ -569,21 +588,27 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
     for (int u = 0; u < 8; u++) {
       if (i0 + u * NTH + t < len) {
         const uint32_t q = slot(k[u]);
-        atomicAdd(&sm.cnt[q >> 1], 1u << (16 * (q & 1)));
+        if constexpr (C16) atomicAdd(&sm.cnt[q >> 1], 1u << (16 * (q & 1)));
+        else atomicAdd(&sm.cnt[q], 1u);
       }
     }
   }
   __syncthreads();
-  // exclusive scan of the slot counts (16-bit halves), and the fullest slot
+  // exclusive scan of the slot counts, and the fullest slot
   {
     constexpr int PER = W / NTH;
     uint32_t v[PER], sum = 0, mxc = 0;
 #pragma unroll
     for (int j = 0; j < PER; j++) {
       v[j] = sm.cnt[t * PER + j];
-      const uint32_t a0 = v[j] & 0xFFFFu, a1 = v[j] >> 16;
-      sum += a0 + a1;
-      mxc = max(mxc, max(a0, a1));
+      if constexpr (C16) {
+        const uint32_t a0 = v[j] & 0xFFFFu, a1 = v[j] >> 16;
+        sum += a0 + a1;
+        mxc = max(mxc, max(a0, a1));
+      } else {
+        sum += v[j];
+        mxc = max(mxc, v[j]);
+      }
     }
     uint32_t tot;
     uint32_t run = block_excl_scan<NTH>(sum, (uint32_t*)sm.red, &tot);
@@ -593,9 +618,14 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
     if (lane_id() == 0 && wm > ROUNDS_MAX_FILL) atomicOr(&sm.flag, 1u);
 #pragma unroll
     for (int j = 0; j < PER; j++) {
-      const uint32_t a0 = v[j] & 0xFFFFu;
-      sm.cnt[t * PER + j] = run | ((run + a0) << 16);   // starts of slots 2w and 2w+1
-      run += a0 + (v[j] >> 16);
+      if constexpr (C16) {
+        const uint32_t a0 = v[j] & 0xFFFFu;
+        sm.cnt[t * PER + j] = run | ((run + a0) << 16);   // starts of slots 2w and 2w+1
+        run += a0 + (v[j] >> 16);
+      } else {
+        sm.cnt[t * PER + j] = run;
+        run += v[j];
+      }
     }
   }
   __syncthreads();
@@ -613,9 +643,9 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
     return a;
   };
   // round boundaries, taken while the counters still hold the slot starts
-  // (len < 2^16 and CR > 2^14: at most four rounds)
   const uint32_t rounds = (len + CR - 1) / CR;
-  if (t <= (int)rounds) {
+  for (uint32_t t2 = t; t2 <= rounds; t2 += NTH) {
+    const int t = (int)t2;
     const uint32_t b = (t == 0) ? 0u : ((uint32_t)t < rounds ? first_slot(t * CR) : (uint32_t)S);
     sm.rslot[t] = b;
     sm.rbase[t] = b < (uint32_t)S ? get(b) : len;
@@ -626,11 +656,7 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
     const uint32_t qa = sm.rslot[r], qb = sm.rslot[r + 1], base = sm.rbase[r];
     auto place = [&](uint32_t k) {
       const uint32_t q = slot(k);
-      if (rounds == 1 || (q >= qa && q < qb)) {
-        const uint32_t sft = 16 * (q & 1);
-        const uint32_t old = atomicAdd(&sm.cnt[q >> 1], 1u << sft);
-        sm.placed[((old >> sft) & 0xFFFFu) - base] = k;
-      }
+      if (rounds == 1 || (q >= qa && q < qb)) sm.placed[inc(q) - base] = k;
     };
     for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
       uint32_t k[8];
@@ -685,8 +711,34 @@ __global__ void __launch_bounds__(WIDE_BNT) k_wide_bucket(LevelArgs a, WideArgs 
     for (uint32_t i = nt1 + t; i < end; i += WIDE_BNT) out[i] = v;
   }
   const uint32_t sz = nt1 - nt0;
+  if (sz > WIDE_BMAX && a.next_segs) {
+    // larger than one work-group sorts: the next level splits the keys
+    // between the tie runs again (they are in the workspace copy, where it
+    // reads)
+    if (t == 0) {
+      atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)(end - beg - sz));
+      const uint32_t slot = atomicAdd(&a.next_ctl->nsegs, 1u);
+      if (slot < a.next_cap) {
+        SegDesc nd = {};
+        nd.beg = nt0;
+        nd.len = sz;
+        nd.seed = derive_seed(a.segs[0].seed, 1, b);
+        nd.depth = 1;
+        nd.parent_bkt = b;
+        a.next_segs[slot] = nd;
+      } else {
+        atomicOr(&a.gctl->status, ST_LIST_FULL);
+        const uint32_t k = atomicAdd(a.nleft, 1u);
+        a.left[k] = SmallEnt{nt0, sz, b};
+      }
+    }
+    return;
+  }
   bool done = sz == 0;
-  if (!done) done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP>(w.fine + nt0, out + nt0, sz, w.kout, sm, lo_k, lo, hi_k, hi);
+  if (!done && sz <= WIDE_BMAX)
+    done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP>(w.fine + nt0, out + nt0, sz, w.kout, sm, lo_k, lo, hi_k, hi);
+  else if (!done)
+    done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP, false>(w.fine + nt0, out + nt0, sz, w.kout, sm, lo_k, lo, hi_k, hi);
   if (t == 0) {
     if (done) {
       atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)(end - beg));
@@ -706,8 +758,12 @@ __global__ void __launch_bounds__(WIDE_BNT) k_bucket_rounds_keys(LevelArgs a) {
   const uint32_t nl = *a.nleft;
   for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
     const SmallEnt e = a.left[li];
-    const bool done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP>((const uint32_t*)a.dst + e.beg, (uint32_t*)a.out + e.beg,
-                                                             e.len, a.kout, sm, false, 0u, false, 0u);
+    const uint32_t* src = (const uint32_t*)a.dst + e.beg;
+    uint32_t* dst = (uint32_t*)a.out + e.beg;
+    const bool done = e.len <= WIDE_BMAX
+                          ? slot_sort_rounds<WIDE_BNT, WIDE_BCAP>(src, dst, e.len, a.kout, sm, false, 0u, false, 0u)
+                          : slot_sort_rounds<WIDE_BNT, WIDE_BCAP, false>(src, dst, e.len, a.kout, sm, false, 0u,
+                                                                         false, 0u);
     if (threadIdx.x == 0) {
       if (done) {
         atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)e.len);

@@ -116,14 +116,26 @@ def test_segmented_graph_capture_replays():
 
 
 def test_full_size_2p26_int32_bench_config():
-    """The benchmarked configuration at its full size, bit-exact."""
+    """The benchmarked configurations at full size, bit-exact: the one-pass
+    split (p = 128), the wide split (p = 4096), and the wide split whose
+    buckets of ~2^16 keys go one level down (p = 1024, s = 4), also in
+    place."""
     keys = workloads.keys_2p26(2**26, "uniform", workloads.seed_for(1, 0), np.int32)
     want = keys[oracle.stable_perm(keys)]
     kd = torch.from_numpy(keys).cuda()
-    for p, s in [(128, 16), (4096, 16)]:
+    for p, s in [(128, 16), (4096, 16), (1024, 4)]:
         note(f"2^26 int32 p={p} s={s}")
-        out = api.sort_keys(kd, api.params(p=p, s=s, seed=1234))
+        prm = api.params(p=p, s=s, seed=1234)
+        ws = api._workspace(api.workspace_size(2**26, N.SS_I32, N.SS_V_NONE, prm), kd.device)
+        out = api.sort_keys(kd, prm, ws=ws)
         np.testing.assert_array_equal(out.cpu().numpy(), want)
+        if p == 1024:
+            levels = api.level_stats(ws)
+            assert len(levels) == 2 and levels[1]["keys"] > 0
+            note("2^26 int32 p=1024 s=4 in place")
+            kin = kd.clone()
+            api.sort_keys(kin, prm, out=kin, ws=ws)
+            np.testing.assert_array_equal(kin.cpu().numpy(), want)
 
 
 def test_full_size_2p27_pairs_stable():

@@ -135,3 +135,21 @@ def test_wide_regular_sampling():
     np.testing.assert_array_equal(st["counts"], ref["counts"])
     assert st["counts"].max() <= oracle.lemma1_bounds(n, 1024, 1)[1]
     np.testing.assert_array_equal(to_host(out, np.uint32), keys[ref["perm"]])
+
+
+def test_wide_buckets_beyond_16_bit_counters():
+    """No level below (SS_F_NO_RECURSION), p = 1024, s = 4 on 2^25 + 12345
+    keys: buckets average 32K keys and many exceed 65535, which the bucket
+    sort takes with 32-bit slot counters in several rounds.  Counts equal
+    the oracle's; output bit-exact."""
+    n = (1 << 25) + 12345
+    keys = workloads.keys_2p26(n, "uniform", workloads.seed_for(5, 3), np.int32)
+    kd = torch.from_numpy(keys).cuda()
+    prm = api.params(p=1024, s=4, seed=29, flags=N.SS_F_NO_RECURSION)
+    note("wide 2^25 p=1024 s=4 no recursion")
+    out, st, info = api.stages(kd, prm)
+    ref = oracle.stages(keys, 1024, 4, oracle.RANDOM, 29)
+    assert info.p_eff == 1024
+    np.testing.assert_array_equal(st["counts"], ref["counts"])
+    assert st["counts"].max() > 65535
+    np.testing.assert_array_equal(out.cpu().numpy(), keys[ref["perm"]])
