@@ -269,7 +269,7 @@ struct Plan {
   bool wide = false;
   uint32_t wide_W = 0;
   size_t o_whf = 0, o_whf_part = 0, o_wha = 0, o_wha_part = 0, o_wkeys = 0, o_wtags = 0, o_wcells = 0, o_whdr = 0;
-  size_t o_tmp2 = 0;       // wide split with a level below and input == output: first-pass buffer
+  size_t o_tmp2 = 0;       // wide split with input == output: a second copy
   size_t bytes = 0;
   ~Plan() { delete nested; }
 };
@@ -357,10 +357,11 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   }
   // (the wide split's bucket sort takes any size in rounds; a level below
   // pays once buckets would need many rounds)
-  plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp, P->wide ? 2 * WIDE_BMAX : 0);
-  // the wide split's buckets must end up in tmp when a level below reads
-  // them; with input == output its first pass then needs a buffer of its own
-  if (P->wide && P->lp.nlev > 1) P->o_tmp2 = L.take((size_t)ty.KW * n);
+  plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp, P->wide ? WIDE_LEVEL_MIN : 0);
+  // with input == output the wide split's first pass needs a buffer of its
+  // own: the stage, or the fine buckets (which a bucket sort of several
+  // rounds re-reads while it writes the output)
+  if (P->wide) P->o_tmp2 = L.take((size_t)ty.KW * n);
   if (P->regular) {
     // blocks sorted with their in-block index as payload (Alg. 1 step 1)
     P->o_regk = L.take((size_t)ty.KW * n);
@@ -498,10 +499,10 @@ uint32_t grid_of(uint64_t work, uint32_t per, uint32_t cap) {
 
 // The wide split of a single keys-only sort (level 0 after its splitter
 // tree): count, scans, two split passes, bucket sorts.  The keys travel
-// input -> stage -> fine -> output.  Without a level below, input == output
-// puts the stage in the workspace copy and sorts the buckets in place; with
-// a level below, the fine buckets are always in the workspace copy (where
-// that level reads them).
+// input -> stage -> fine -> output.  With a level below, the fine buckets
+// are always in the workspace copy tmp (where that level reads them);
+// without one, input == output puts stage and fine buckets in the two
+// workspace copies, so no pass reads what it writes.
 int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, int exp, hipStream_t st) {
   WideArgs w{};
   const bool inplace = in == out;
@@ -516,7 +517,7 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
     w.fine = tmp;
   } else {
     w.stage = inplace ? tmp : (uint32_t*)out;
-    w.fine = inplace ? (uint32_t*)out : tmp;
+    w.fine = inplace ? (uint32_t*)(ws + P.o_tmp2) : tmp;
   }
   w.out = out;
   w.n = (uint32_t)P.n;

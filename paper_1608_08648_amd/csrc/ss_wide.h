@@ -52,6 +52,11 @@ constexpr uint32_t WIDE_TB = 65536;            // nominal keys per piece of the 
 constexpr int WIDE_BNT = 1024;
 constexpr int WIDE_BCAP = 30720;
 constexpr uint32_t WIDE_BMAX = 65535;          // largest bucket the round-based slot sort takes
+// expected largest bucket up to which the wide split sorts every bucket in
+// rounds; above it a level below takes the buckets past WIDE_BMAX (on 2^26
+// int32 keys with p = 1024 the rounds win at an estimate of 2^17 keys and
+// lose at 1.2 * 2^17 and more)
+constexpr uint32_t WIDE_LEVEL_MIN = 1u << 17;
 
 struct WideHdr { uint32_t kmin, kmax, sh, ncell; };
 

@@ -153,3 +153,19 @@ def test_wide_buckets_beyond_16_bit_counters():
     np.testing.assert_array_equal(st["counts"], ref["counts"])
     assert st["counts"].max() > 65535
     np.testing.assert_array_equal(out.cpu().numpy(), keys[ref["perm"]])
+
+
+def test_wide_in_place_buckets_in_rounds():
+    """keys_in == keys_out without a level below (SS_F_NO_RECURSION), p =
+    1024, s = 4 on 2^25 + 3 keys: buckets average 32K keys, so the bucket
+    sort re-reads most of them in several rounds (some with 32-bit slot
+    counters) while it writes the output; it must read a copy the output
+    does not overwrite."""
+    n = (1 << 25) + 3
+    keys = workloads.keys_2p26(n, "uniform", workloads.seed_for(5, 4), np.int32)
+    kd = torch.from_numpy(keys).cuda()
+    prm = api.params(p=1024, s=4, seed=31, flags=N.SS_F_NO_RECURSION)
+    note("wide in place 2^25 p=1024 s=4 rounds")
+    out = api.sort_keys(kd, prm, out=kd)
+    assert out.data_ptr() == kd.data_ptr()
+    np.testing.assert_array_equal(kd.cpu().numpy(), _sorted_by_oracle(keys))
