@@ -60,6 +60,13 @@ enum { SS_RANDOM = 0,   /* Alg. 2: p*s-1 keys drawn uniformly (with replacement)
 #define SS_F_NO_WIDE        8u  /* keys-only sorts of 4-byte keys with p >= 1024 move the keys in
                                    two passes (64 coarse buckets, then p/64 fine ones); this flag
                                    keeps the one-pass split instead (for comparisons) */
+#define SS_F_SORT_FIRST    16u  /* the organisation Alg. 1 and Alg. 2 state: sort the p blocks
+                                   first (step 1), place the splitters in each sorted block by
+                                   binary search (step 4), and form bucket j from the p runs the
+                                   splitters cut out of the blocks (step 5).  4-byte keys without
+                                   payload only (SS_EINVAL otherwise); no level below.  Without
+                                   the flag the keys are classified and moved unsorted (the
+                                   split-first organisation, the default). */
 
 /* return codes */
 enum { SS_OK = 0, SS_EINVAL = -1, SS_EWORKSPACE = -2, SS_EHIP = -3, SS_EDEVICE = -4 };

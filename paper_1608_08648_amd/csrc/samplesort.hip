@@ -6,6 +6,7 @@
 #include "ss_kernels.h"
 #include "ss_wide.h"
 #include "ss_pairs.h"
+#include "ss_sortfirst.h"
 
 #include <hip/hip_runtime.h>
 
@@ -46,12 +47,12 @@ int fail(int code, const char* fmt, ...) {
 enum ProfKind {
   PK_INIT, PK_PLAN, PK_SAMPLE, PK_SAMPLE_SORT, PK_SAMPLE_MERGE, PK_TREE, PK_CLASSIFY, PK_SCAN, PK_SCATTER,
   PK_BUCKET_SORT, PK_BUCKET_LEFT, PK_SMALL_SORT, PK_BLOCK_SORT_REGULAR, PK_GRAD, PK_SPLIT_COARSE, PK_SPLIT_FINE,
-  PK_COUNT
+  PK_SF_SEARCH, PK_SF_GATHER, PK_COUNT
 };
 const char* const PROF_NAMES[PK_COUNT] = {
     "init", "plan", "sample", "sample_sort", "sample_merge", "tree", "classify", "scan", "scatter",
     "bucket_sort", "bucket_leftover", "small_sort", "regular_blocks", "scatter_grad", "split_coarse",
-    "split_fine"};
+    "split_fine", "sf_search", "sf_gather"};
 
 struct Prof {
   bool on = false;
@@ -270,6 +271,9 @@ struct Plan {
   uint32_t wide_W = 0;
   size_t o_whf = 0, o_whf_part = 0, o_wha = 0, o_wha_part = 0, o_wkeys = 0, o_wtags = 0, o_wcells = 0, o_whdr = 0;
   size_t o_tmp2 = 0;       // wide split with input == output: a second copy
+  // sort-first organisation: sorted blocks (o_regk, o_regi), the run table and the buckets
+  bool sortfirst = false;
+  size_t o_sfpos = 0, o_sfbkt = 0;
   size_t bytes = 0;
   ~Plan() { delete nested; }
 };
@@ -297,6 +301,8 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   P->n = n;
   P->prm = prm;
   if (n >= (1ull << 32)) return fail(SS_EINVAL, "n = %llu: at most 2^32-1 keys per array", (unsigned long long)n);
+  if ((prm.flags & SS_F_SORT_FIRST) && !(ty.KW == 4 && ty.VW == 0))
+    return fail(SS_EINVAL, "SS_F_SORT_FIRST: 4-byte keys without payload only");
   const uint32_t C = small_cap(ty.KW, ty.VW);
   Layout L;
   P->o_ctl = L.take(sizeof(Ctl));
@@ -316,6 +322,8 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   }
   const uint32_t p = P->p_eff;
   P->s = prm.s;
+  P->sortfirst = (prm.flags & SS_F_SORT_FIRST) != 0;
+  if (P->sortfirst && p > SF_PMAX) return fail(SS_EINVAL, "SS_F_SORT_FIRST: p = %u, at most %u", p, SF_PMAX);
   uint64_t est;
   if (P->regular) {
     P->m = (uint64_t)prm.s * p * p;
@@ -338,10 +346,11 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   }
   P->o_tmp = L.take((size_t)ty.KW * n);
   P->o_vtmp = ty.VW ? L.take((size_t)ty.VW * n) : 0;
-  bool recurse = !(prm.flags & SS_F_NO_RECURSION);
+  bool recurse = !(prm.flags & SS_F_NO_RECURSION) && !P->sortfirst;
   // wide split: many buckets of keys only; buckets beyond the round-based
   // slot sort's 65535 keys go one level down
-  P->wide = ty.VW == 0 && ty.KW == 4 && p >= 1024 && p <= (uint32_t)WIDE_PMAX && !(prm.flags & SS_F_NO_WIDE);
+  P->wide = ty.VW == 0 && ty.KW == 4 && p >= 1024 && p <= (uint32_t)WIDE_PMAX && !(prm.flags & SS_F_NO_WIDE) &&
+            !P->sortfirst;
   if (P->wide) {
     const uint64_t W = cdiv(n, WIDE_TILE);
     P->wide_W = (uint32_t)W;
@@ -362,7 +371,11 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   // own: the stage, or the fine buckets (which a bucket sort of several
   // rounds re-reads while it writes the output)
   if (P->wide) P->o_tmp2 = L.take((size_t)ty.KW * n);
-  if (P->regular) {
+  if (P->sortfirst) {
+    P->o_sfpos = L.take(4 * (size_t)p * (p + 1));
+    P->o_sfbkt = L.take(8 * (size_t)p);
+  }
+  if (P->regular || P->sortfirst) {
     // blocks sorted with their in-block index as payload (Alg. 1 step 1)
     P->o_regk = L.take((size_t)ty.KW * n);
     P->o_regi = L.take(4 * n);
@@ -390,6 +403,7 @@ int plan_segmented(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, cons
   P->prm = prm;
   P->segmented = true;
   P->nseg = nseg;
+  if (prm.flags & SS_F_SORT_FIRST) return fail(SS_EINVAL, "SS_F_SORT_FIRST: single arrays only");
   if (maxlen == 0 || maxlen > total) maxlen = total;
   P->maxlen = maxlen;
   if (maxlen >= (1ull << 32)) return fail(SS_EINVAL, "segments of 2^32 or more keys are not supported");
@@ -565,6 +579,37 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   return SS_OK;
 }
 
+// Sort-first organisation (steps 4 and 5 of Alg. 1 / Alg. 2; step 1 ran
+// before the sample, steps 2-3 built the splitter tree): place the splitters
+// in the sorted blocks, gather each bucket's runs into tmp, sort each bucket
+// into the output.
+int run_sort_first(const Plan& P, char* ws, LevelArgs a, void* out, int exp, hipStream_t st) {
+  SfArgs f{};
+  f.bkeys = (const uint32_t*)(ws + P.o_regk);
+  f.bidx = (const uint32_t*)(ws + P.o_regi);
+  f.tree = (const uint64_t*)a.tree;
+  f.pos = (uint32_t*)(ws + P.o_sfpos);
+  f.bkt = (uint2*)(ws + P.o_sfbkt);
+  f.stage = (uint32_t*)(ws + P.o_tmp);
+  f.n = P.n;
+  f.p = P.p_eff;
+  f.lgp = 31 - __builtin_clz(P.p_eff);
+  f.kind = P.ty.kind;
+  const uint64_t bmax = cdiv(P.n, f.p);   // longest block
+  f.lds_keys = bmax <= SF_LDS_KEYS ? (uint32_t)bmax : 0u;
+  LAUNCH(PK_SF_SEARCH, k_sf_search, dim3(f.p), dim3(SF_NT), 4 * (size_t)f.lds_keys, st, f);
+  LAUNCH_CHECK();
+  LAUNCH(PK_SF_GATHER, k_sf_gather, dim3(f.p), dim3(SF_GNT), 0, st, f, exp ? a.exp_counts : nullptr);
+  LAUNCH_CHECK();
+  a.dst = f.stage;
+  a.out = out;
+  LAUNCH(PK_BUCKET_SORT, k_sf_bucket, dim3(f.p), dim3(WIDE_BNT), 0, st, a, f);
+  LAUNCH_CHECK();
+  LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<4>), dim3(std::min<uint32_t>(f.p, 512)), dim3(NT), 0, st, a, 0);
+  LAUNCH_CHECK();
+  return SS_OK;
+}
+
 template <int KW, int VW>
 int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st) {
   const uint32_t Cs = sample_cap(KW);
@@ -607,6 +652,7 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
     }
     LAUNCH_CHECK();
     if constexpr (KW == 4 && VW == 0) {
+      if (l == 0 && P.sortfirst) return run_sort_first(P, ws, a, out, exp, st);
       if (l == 0 && P.wide) {
         int rc = run_wide(P, ws, a, in, out, exp, st);
         if (rc) return rc;
@@ -693,7 +739,7 @@ int run_single(const Plan& P, char* ws, const void* in, const void* vin, void* o
     LAUNCH_CHECK();
     return SS_OK;
   }
-  if (P.regular) {
+  if (P.regular || P.sortfirst) {
     // Alg. 1 step 1: sort the p blocks (key, in-block index) with the segmented path
     int64_t* boff = (int64_t*)(ws + P.o_regoff);
     LAUNCH(PK_INIT, k_block_offsets, dim3(grid_of(P.p_eff + 1, 256, 64)), dim3(256), 0, st, boff, (uint64_t)P.n,

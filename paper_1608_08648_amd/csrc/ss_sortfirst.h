@@ -1,0 +1,164 @@
+// Sort-first organisation of the method, as Alg. 1 and Alg. 2 state it, for
+// 4-byte keys without payload:
+//   step 1  the p blocks [floor(k n / p), floor((k+1) n / p)) are sorted by
+//           (key, in-block index) (the segmented path, index as payload);
+//   steps 2-3 the sample (regular: from the sorted blocks, Alg. 1; random:
+//           from the input, Alg. 2) and its p - 1 splitters, as in the
+//           split-first path;
+//   step 4  every splitter is placed in every sorted block by binary search
+//           (the alternative the analysis of step 4 gives to merging), which
+//           cuts block k into the runs X_{k,j};
+//   step 5  bucket j gathers its p runs X_{0,j} .. X_{p-1,j} (in block order)
+//           and sorts them in LDS with the round-based slot sort; the
+//           concatenation of the buckets is the output.
+// Keys compare as (ord(key), global index), the same total order as the
+// split-first classification, so bucket j holds exactly the keys that
+// classification puts in bucket j.
+#pragma once
+#include "ss_wide.h"
+
+namespace ss {
+
+constexpr int SF_NT = 1024;                // threads of the search kernel
+constexpr uint32_t SF_LDS_KEYS = 16384;    // sorted block keys the search holds in LDS (at most 64 KB)
+constexpr uint32_t SF_PMAX = 4096;         // largest p: the gather kernel's run table (32 KB)
+constexpr int SF_GNT = 512;                // threads of the gather kernel
+
+struct SfArgs {
+  const uint32_t* bkeys;   // step 1: the sorted blocks (keys as given)
+  const uint32_t* bidx;    // in-block index of each sorted key
+  const uint64_t* tree;    // Eytzinger tree of the splitters, slot k in [1, p): (ord << 32) | tag
+  uint32_t* pos;           // p rows of p + 1: pos[k (p+1) + j] = start of X_{k,j} in sorted block k
+  uint2* bkt;              // per bucket: (output start, size)
+  uint32_t* stage;         // step 5: the gathered buckets, as ord keys
+  uint64_t n;
+  uint32_t p, lgp;
+  int kind;                // key kind (to_ord / from_ord)
+  uint32_t lds_keys;       // search: the longest block when it fits SF_LDS_KEYS (the LDS launched), else 0
+};
+
+__device__ __forceinline__ uint64_t sf_block_start(uint64_t n, uint32_t p, uint32_t k) {
+  return ((uint64_t)k * n) / p;
+}
+
+// splitter of rank r (1 <= r < p) from the Eytzinger tree
+__device__ __forceinline__ uint64_t sf_splitter(const uint64_t* tree, uint32_t lgp, uint32_t r) {
+  const uint32_t z = __builtin_ctz(r);
+  return tree[(1u << (lgp - 1 - z)) + (r >> (z + 1))];
+}
+
+// Step 4: one work-group per sorted block k writes pos[k][0..p]: the number
+// of the block's keys not above each splitter in (key, index) order (a key
+// belongs to the bucket of the first splitter not below it, so a sampled
+// key equal to splitter j stays in bucket j - 1, as the classification
+// #{splitters < (key, index)} has it).
+__global__ void __launch_bounds__(SF_NT) k_sf_search(SfArgs f) {
+  extern __shared__ uint32_t sk[];   // f.lds_keys keys
+  const uint32_t k = blockIdx.x;
+  if (k >= f.p) return;
+  const uint64_t bs = sf_block_start(f.n, f.p, k);
+  const uint32_t len = (uint32_t)(sf_block_start(f.n, f.p, k + 1) - bs);
+  const bool lds = len <= f.lds_keys;
+  if (lds)
+    for (uint32_t i = threadIdx.x; i < len; i += SF_NT) sk[i] = to_ord(f.bkeys[bs + i], f.kind);
+  __syncthreads();
+  uint32_t* row = f.pos + (uint64_t)k * (f.p + 1);
+  for (uint32_t r = threadIdx.x; r <= f.p; r += SF_NT) {
+    uint32_t res = len;
+    if (r == 0) {
+      res = 0;
+    } else if (r < f.p) {
+      const uint64_t sp = sf_splitter(f.tree, f.lgp, r);
+      const uint32_t skey = (uint32_t)(sp >> 32);
+      const uint64_t stag = (uint32_t)sp;
+      uint32_t a = 0, z = len;   // first position whose key is above the splitter
+      while (a < z) {
+        const uint32_t m = (a + z) >> 1;
+        const uint32_t km = lds ? sk[m] : to_ord(f.bkeys[bs + m], f.kind);
+        const bool upto = km < skey || (km == skey && bs + f.bidx[bs + m] <= stag);
+        if (upto) a = m + 1;
+        else z = m;
+      }
+      res = a;
+    }
+    row[r] = res;
+  }
+}
+
+// Step 5, first half: one work-group per bucket j finds its runs X_{k,j},
+// their places in the bucket (a scan over k) and the bucket's output start
+// (the keys of all blocks up to splitter j), and copies the runs, in block
+// order, to stage[start ..] as ord keys.
+__global__ void __launch_bounds__(SF_GNT) k_sf_gather(SfArgs f, uint64_t* exp_counts) {
+  __shared__ uint32_t off[SF_PMAX + 1];    // start of run k in the bucket
+  __shared__ uint32_t src[SF_PMAX];        // start of run k in the sorted blocks
+  __shared__ uint32_t red[2 * (SF_GNT / WAVE)];
+  const uint32_t j = blockIdx.x, p = f.p;
+  if (j >= p) return;
+  const int t = threadIdx.x;
+  const uint32_t per = (p + SF_GNT - 1) / SF_GNT;   // consecutive runs per thread
+  const uint32_t k0 = min(p, (uint32_t)t * per), k1 = min(p, k0 + per);
+  uint32_t cnt = 0, below = 0;
+  for (uint32_t k = k0; k < k1; k++) {
+    const uint32_t* row = f.pos + (uint64_t)k * (p + 1);
+    const uint32_t a = row[j], b = row[j + 1];
+    src[k] = (uint32_t)sf_block_start(f.n, p, k) + a;
+    off[k] = b - a;            // (length until the scan)
+    cnt += b - a;
+    below += a;
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan<SF_GNT>(cnt, red, &tot);
+  __syncthreads();
+  for (uint32_t k = k0; k < k1; k++) {
+    const uint32_t l = off[k];
+    off[k] = run;
+    run += l;
+  }
+  if (t == 0) off[p] = tot;
+  uint32_t start;
+  block_excl_scan<SF_GNT>(below, red, &start);   // (total of the keys up to splitter j)
+  __syncthreads();
+  for (uint32_t e = t; e < tot; e += SF_GNT) {
+    uint32_t a = 0, z = p;   // last run whose start is <= e
+    while (z - a > 1) {
+      const uint32_t m = (a + z) >> 1;
+      if (off[m] <= e) a = m;
+      else z = m;
+    }
+    f.stage[start + e] = to_ord(f.bkeys[src[a] + (e - off[a])], f.kind);
+  }
+  if (t == 0) {
+    f.bkt[j] = make_uint2(start, tot);
+    if (exp_counts) exp_counts[j] = tot;
+  }
+}
+
+// Step 5, second half: one work-group per bucket sorts its gathered keys
+// (they lie between the keys of splitters j and j + 1, both included) with
+// the round-based slot sort; crowded buckets go to the radix sort's list.
+__global__ void __launch_bounds__(WIDE_BNT) k_sf_bucket(LevelArgs a, SfArgs f) {
+  __shared__ SlotRoundsLds<WIDE_BCAP> sm;
+  const uint32_t j = blockIdx.x;
+  if (j >= f.p) return;
+  const uint2 e = f.bkt[j];
+  const bool lo_k = j >= 1, hi_k = j + 1 < f.p;
+  const uint32_t lo = lo_k ? (uint32_t)(sf_splitter(f.tree, f.lgp, j) >> 32) : 0u;
+  const uint32_t hi = hi_k ? (uint32_t)(sf_splitter(f.tree, f.lgp, j + 1) >> 32) : 0u;
+  uint32_t* out = (uint32_t*)a.out + e.x;
+  bool done = e.y == 0;
+  if (!done && e.y <= WIDE_BMAX)
+    done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP>(f.stage + e.x, out, e.y, f.kind, sm, lo_k, lo, hi_k, hi);
+  else if (!done)
+    done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP, false>(f.stage + e.x, out, e.y, f.kind, sm, lo_k, lo, hi_k, hi);
+  if (threadIdx.x == 0) {
+    if (done) {
+      atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)e.y);
+    } else {
+      const uint32_t k = atomicAdd(a.nleft, 1u);
+      a.left[k] = SmallEnt{e.x, e.y, j};
+    }
+  }
+}
+
+}  // namespace ss

@@ -107,6 +107,23 @@ def test_bad_types_rejected():
     assert _ws(100, N.SS_I32, 9)[0] == N.SS_EINVAL
 
 
+def test_sort_first_flag():
+    """SS_F_SORT_FIRST (the organisation of Alg. 1 / Alg. 2: blocks sorted
+    first) takes 4-byte keys without payload, plans no level below, and
+    its workspace holds the sorted blocks (keys and in-block indices) and
+    the p x (p + 1) run table."""
+    SF = N.SS_F_SORT_FIRST
+    for kt in (N.SS_I32, N.SS_U32, N.SS_F32):
+        rc, b = _ws(2**26, kt, p=4096, s=16, flags=SF)
+        assert rc == 0 and b >= 3 * 4 * 2**26 + 4 * 4096 * 4097
+        for mode in (0, 1):
+            rc, info = _layout(2**22, kt, p=256, s=4, sampling=mode, flags=SF)
+            assert rc == 0 and info.levels == 0 and info.p_eff == 256
+    assert _ws(2**20, N.SS_U64, flags=SF)[0] == N.SS_EINVAL
+    assert _ws(2**20, N.SS_I32, N.SS_V_B32, flags=SF)[0] == N.SS_EINVAL
+    assert "SORT_FIRST" in N.last_error()
+
+
 def _prm():
     return N.Params(p=1024, s=8, sampling=0, stable=1, seed=0, flags=0, tile=0)
 

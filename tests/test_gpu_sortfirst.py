@@ -1,0 +1,108 @@
+"""GPU: the sort-first organisation (SS_F_SORT_FIRST), Alg. 1 / Alg. 2 as
+stated: blocks sorted first (step 1), the splitters placed in every sorted
+block by binary search (step 4), bucket j formed from the runs X_{k,j} and
+sorted (step 5).  Bit-exact against the oracle; bucket counts against the
+oracle's stages (the same (key, index) order decides both)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1608_08648_amd import api
+from paper_1608_08648_amd import native as N
+from paper_1608_08648_amd import workloads
+from tests.gpu_util import note, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SF = N.SS_F_SORT_FIRST
+
+
+def _sorted_by_oracle(keys):
+    return keys[oracle.stable_perm(keys)]
+
+
+@pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS)
+def test_sort_first_six_distributions(dist):
+    """2^22 + 12345 int32 keys (ragged blocks) in each distribution, p =
+    1024, s = 8, random sampling: bit-exact, every key in a bucket."""
+    n = (1 << 22) + 12345
+    keys = workloads.keys_2p26(n, dist, workloads.seed_for(6, workloads.DISTRIBUTIONS.index(dist)), np.int32)
+    kd = torch.from_numpy(keys).cuda()
+    prm = api.params(p=1024, s=8, seed=72, flags=SF)
+    ws = api._workspace(api.workspace_size(n, N.SS_I32, N.SS_V_NONE, prm), kd.device)
+    note(f"sort-first {dist} n={n}")
+    out = api.sort_keys(kd, prm, ws=ws)
+    np.testing.assert_array_equal(out.cpu().numpy(), _sorted_by_oracle(keys))
+
+
+@pytest.mark.parametrize("mode,p,s", [(oracle.RANDOM, 256, 4), (oracle.REGULAR, 256, 4), (oracle.RANDOM, 4096, 2)])
+@pytest.mark.parametrize("mod", [0, 1000])
+def test_sort_first_counts_equal_oracle(mode, p, s, mod):
+    """Bucket counts (the sizes of the concatenated runs X_{k,j}) and
+    splitters equal the oracle's, with distinct keys and with heavy
+    duplicates (keys mod 1000), under both sampling rules."""
+    n = 1 << 20
+    keys = workloads.uniform_u32(n, workloads.seed_for(0) + 11 + mod)
+    if mod:
+        keys = (keys % np.uint32(mod)).astype(np.uint32)
+    kd, kt = to_dev(keys)
+    sampling = "regular" if mode == oracle.REGULAR else "random"
+    prm = api.params(p=p, s=s, seed=5, sampling=sampling, flags=SF)
+    note(f"sort-first stages mode={mode} p={p} s={s} mod={mod}")
+    out, st, info = api.stages(kd, prm, key_type=kt)
+    ref = oracle.stages(keys, p, s, mode, 5)
+    assert info.p_eff == p
+    np.testing.assert_array_equal(st["spl_ord"], ref["spl_ord"])
+    np.testing.assert_array_equal(st["spl_tag"], ref["spl_tag"])
+    np.testing.assert_array_equal(st["counts"], ref["counts"])
+    np.testing.assert_array_equal(to_host(out, np.uint32), keys[ref["perm"]])
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.uint32])
+def test_sort_first_key_types(dtype):
+    """float32 (totalOrder image: negatives, -0.0/+0.0) and uint32 keys."""
+    n = (1 << 21) + 7
+    g = np.random.default_rng(13)
+    if dtype == np.float32:
+        keys = g.standard_normal(n).astype(np.float32)
+        keys[::1000] = -0.0
+        keys[1::1000] = 0.0
+    else:
+        keys = g.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    kd, kt = to_dev(keys)
+    prm = api.params(p=512, s=16, seed=4, flags=SF)
+    note(f"sort-first {np.dtype(dtype).name}")
+    out = api.sort_keys(kd, prm, key_type=kt)
+    want = _sorted_by_oracle(keys)
+    np.testing.assert_array_equal(to_host(out, dtype).view(np.uint32), want.view(np.uint32))
+
+
+def test_sort_first_in_place_and_large_blocks():
+    """keys_in == keys_out, and blocks of 64K keys (p = 64 on 2^22 keys):
+    the splitter search then runs on the sorted block in global memory (no
+    LDS copy past 16K keys) and buckets of ~64K keys take the slot sort in
+    rounds, some with 32-bit counters."""
+    n = 1 << 22
+    keys = workloads.keys_2p26(n, "gaussian", workloads.seed_for(6, 9), np.int32)
+    kd = torch.from_numpy(keys).cuda()
+    prm = api.params(p=64, s=16, seed=8, flags=SF)
+    note("sort-first in place p=64")
+    out = api.sort_keys(kd, prm, out=kd)
+    assert out.data_ptr() == kd.data_ptr()
+    np.testing.assert_array_equal(kd.cpu().numpy(), _sorted_by_oracle(keys))
+
+
+def test_sort_first_full_size():
+    """2^26 int32 keys, p = 4096, s = 16, random and regular sampling (the
+    benchmarked size): bit-exact."""
+    keys = workloads.keys_2p26(2**26, "uniform", workloads.seed_for(1, 0), np.int32)
+    want = keys[oracle.stable_perm(keys)]
+    kd = torch.from_numpy(keys).cuda()
+    for sampling, p, s in [("random", 4096, 16), ("regular", 1024, 4)]:
+        note(f"sort-first 2^26 {sampling} p={p} s={s}")
+        prm = api.params(p=p, s=s, seed=1234, sampling=sampling, flags=SF)
+        ws = api._workspace(api.workspace_size(2**26, N.SS_I32, N.SS_V_NONE, prm), kd.device)
+        out = api.sort_keys(kd, prm, ws=ws)
+        np.testing.assert_array_equal(out.cpu().numpy(), want)
+        assert api.status(ws) == ""
