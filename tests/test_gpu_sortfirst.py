@@ -106,3 +106,24 @@ def test_sort_first_full_size():
         out = api.sort_keys(kd, prm, ws=ws)
         np.testing.assert_array_equal(out.cpu().numpy(), want)
         assert api.status(ws) == ""
+
+
+@pytest.mark.parametrize("n,p,s,mode", [(5000, 4096, 8, oracle.RANDOM), (3001, 64, 2, oracle.RANDOM),
+                                        (40000, 32, 4, oracle.REGULAR), (1 << 16, 2, 1, oracle.RANDOM)])
+def test_sort_first_small_inputs(n, p, s, mode):
+    """Small inputs forced through the pipeline (SS_F_FORCE_PIPELINE): the
+    effective p shrinks by the paper's preconditions (here to 256, 64, 32
+    and 2), blocks hold a few dozen keys, n is not a multiple of p.  Bucket
+    counts and output equal the oracle's."""
+    keys = workloads.uniform_u32(n, workloads.seed_for(0) + n)
+    keys[::7] = keys[3]                      # duplicates across blocks
+    kd, kt = to_dev(keys)
+    sampling = "regular" if mode == oracle.REGULAR else "random"
+    prm = api.params(p=p, s=s, seed=19, sampling=sampling, flags=SF | N.SS_F_FORCE_PIPELINE)
+    note(f"sort-first small n={n} p={p} s={s} mode={mode}")
+    out, st, info = api.stages(kd, prm, key_type=kt)
+    pe = oracle.p_eff(n, p, s, mode)
+    assert info.p_eff == pe
+    ref = oracle.stages(keys, pe, s, mode, 19)
+    np.testing.assert_array_equal(st["counts"], ref["counts"])
+    np.testing.assert_array_equal(to_host(out, np.uint32), keys[ref["perm"]])
