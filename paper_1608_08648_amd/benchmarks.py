@@ -65,7 +65,8 @@ def bench_pairs(args):
     kd = torch.from_numpy(keys.view(np.int64)).cuda()
     vd = torch.from_numpy(vals.view(np.int32)).cuda()
     ko, vo = torch.empty_like(kd), torch.empty_like(vd)
-    prm = api.params(p=args.p if args.p != 4096 else 1024, s=args.s, seed=9)
+    # (the stable ballot split takes p <= 256; a larger p uses the generic stable split)
+    prm = api.params(p=args.p if args.p != 4096 else 256, s=args.s, seed=9)
     ws = api._workspace(api.workspace_size(n, N.SS_U64, N.SS_V_B32, prm), kd.device)
 
     def step():

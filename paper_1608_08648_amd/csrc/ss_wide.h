@@ -542,6 +542,9 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
   constexpr uint32_t CR = CAP - ROUNDS_MAX_FILL;
   const int t = threadIdx.x;
   if (C16 && len > 65535u) return false;   // (16-bit counters and positions)
+  // a round re-reads the input after earlier rounds wrote the output, so
+  // more than one round needs them apart
+  if ((const void*)in == (const void*)out && len > CR) return false;
   if ((len + (CAP - ROUNDS_MAX_FILL) - 1) / (CAP - ROUNDS_MAX_FILL) > ROUNDS_MAX) return false;
   uint32_t mn = ~0u, mx = 0;
   if (!(lo_known && hi_known)) {
@@ -765,6 +768,16 @@ __global__ void __launch_bounds__(WIDE_BNT) k_bucket_rounds_keys(LevelArgs a) {
     const SmallEnt e = a.left[li];
     const uint32_t* src = (const uint32_t*)a.dst + e.beg;
     uint32_t* dst = (uint32_t*)a.out + e.beg;
+    if ((const void*)src == (const void*)dst && e.len > WIDE_BCAP - ROUNDS_MAX_FILL) {
+      // the level wrote its buckets into the output (odd levels): a bucket
+      // sorted in several rounds reads a copy in tmp, whose range of the
+      // bucket the level's split has already consumed
+      uint32_t* cp = (uint32_t*)a.tmp + e.beg;
+      for (uint32_t i = threadIdx.x; i < e.len; i += WIDE_BNT) cp[i] = src[i];
+      __threadfence();
+      __syncthreads();
+      src = cp;
+    }
     const bool done = e.len <= WIDE_BMAX
                           ? slot_sort_rounds<WIDE_BNT, WIDE_BCAP>(src, dst, e.len, a.kout, sm, false, 0u, false, 0u)
                           : slot_sort_rounds<WIDE_BNT, WIDE_BCAP, false>(src, dst, e.len, a.kout, sm, false, 0u,

@@ -74,3 +74,23 @@ def test_small_input_reports_no_level():
     out = api.sort_keys(kd, prm, ws=ws, key_type=kt)
     np.testing.assert_array_equal(to_host(out, np.uint32), np.sort(keys))
     assert api.level_stats(ws) == []
+
+
+def test_level_below_buckets_in_rounds():
+    """2^26 int32 keys, p = 256, s = 4: the level below splits the 2^18-key
+    buckets with only 4 samples per bucket, so some of its buckets exceed the
+    30,464 keys of one slot-sort round.  Those sit in the output buffer (odd
+    levels write their buckets there) and must be sorted from a copy: a
+    second round re-reads the keys after the first one wrote.  Bit-exact."""
+    keys = workloads.keys_2p26(2**26, "uniform", workloads.seed_for(7, 1), np.int32)
+    want = keys[oracle.stable_perm(keys)]
+    kd = torch.from_numpy(keys).cuda()
+    for s, inplace in [(4, False), (4, True)]:
+        note(f"levels 2^26 p=256 s={s} in_place={inplace}")
+        prm = api.params(p=256, s=s, seed=1234)
+        ws = api._workspace(api.workspace_size(2**26, N.SS_I32, N.SS_V_NONE, prm), kd.device)
+        src = kd.clone() if inplace else kd
+        out = api.sort_keys(src, prm, ws=ws, out=src if inplace else None)
+        np.testing.assert_array_equal(out.cpu().numpy(), want)
+        lv = api.level_stats(ws)
+        assert len(lv) == 2 and lv[1]["keys"] == 2**26
