@@ -56,6 +56,7 @@ const char* const PROF_NAMES[PK_COUNT] = {
 
 struct Prof {
   bool on = false;
+  int force = -1;                   // kind every launch counts as (a nested sort's launches), or -1
   uint32_t mask = ~0u;              // kinds that get events
   int cap = 0, used = 0;
   std::vector<hipEvent_t> ev;       // 2 per launch
@@ -70,6 +71,7 @@ struct ProfScope {
   int slot = -1;
   hipStream_t st;
   ProfScope(int k, hipStream_t s) : st(s) {
+    if (g_prof.force >= 0) k = g_prof.force;
     if (!g_prof.on || !((g_prof.mask >> k) & 1u) || g_prof.used >= g_prof.cap) return;
     slot = g_prof.used++;
     g_prof.kind[slot] = k;
@@ -274,8 +276,14 @@ struct Plan {
   // sort-first organisation: sorted blocks (o_regk, o_regi), the run table and the buckets
   bool sortfirst = false;
   size_t o_sfpos = 0, o_sfbkt = 0;
+  // a large sample of 4-byte keys: packed records and the nested sort that orders them
+  Plan* nested_s = nullptr;
+  size_t o_spack = 0, o_nested_s = 0;
   size_t bytes = 0;
-  ~Plan() { delete nested; }
+  ~Plan() {
+    delete nested;
+    delete nested_s;
+  }
 };
 
 int check_params(const ss_params* prm, ss_params* out) {
@@ -371,6 +379,24 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   // own: the stage, or the fine buckets (which a bucket sort of several
   // rounds re-reads while it writes the output)
   if (P->wide) P->o_tmp2 = L.take((size_t)ty.KW * n);
+  if (ty.KW == 4 && P->lp.big_sample && P->m >= SAMPLE_NESTED_MIN) {
+    // the sample's records (ord key, tag) become 64-bit keys ord << 32 | tag,
+    // whose order is the records' order, and are sorted by a nested sort
+    Types st;
+    parse_types(SS_U64, SS_V_NONE, &st);
+    ss_params sp = prm;
+    sp.p = 256;
+    sp.s = 16;
+    sp.sampling = SS_RANDOM;
+    sp.flags = 0;
+    sp.tile = 0;
+    sp.seed = prm.seed ^ 0x5A3C96E1D2B4F087ull;
+    P->nested_s = new Plan();
+    int rc = plan_single(P->nested_s, P->m, st, sp);
+    if (rc) return rc;
+    P->o_spack = L.take(8 * P->m);
+    P->o_nested_s = L.take(P->nested_s->bytes);
+  }
   if (P->sortfirst) {
     P->o_sfpos = L.take(4 * (size_t)p * (p + 1));
     P->o_sfbkt = L.take(8 * (size_t)p);
@@ -579,6 +605,8 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   return SS_OK;
 }
 
+int run_single_any(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st);
+
 // Sort-first organisation (steps 4 and 5 of Alg. 1 / Alg. 2; step 1 ran
 // before the sample, steps 2-3 built the splitter tree): place the splitters
 // in the sorted blocks, gather each bucket's runs into tmp, sort each bucket
@@ -629,7 +657,27 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
     }
     LAUNCH_CHECK();
     // sample sort and splitter tree
-    if (l == 0 && P.lp.big_sample) {
+    bool sample_done = false;
+    if constexpr (KW == 4) {
+      if (l == 0 && P.nested_s) {
+        uint64_t* pk = (uint64_t*)(ws + P.o_spack);
+        LAUNCH(PK_SAMPLE_SORT, k_pack_sample, dim3(grid_of(P.m, 256, 4096)), dim3(256), 0, st,
+               (const uint32_t*)a.s_ord, (const uint32_t*)a.s_tag, pk, (uint64_t)P.m);
+        LAUNCH_CHECK();
+        g_prof.force = PK_SAMPLE_SORT;
+        const int rc = run_single_any(*P.nested_s, ws + P.o_nested_s, pk, nullptr, pk, nullptr, st);
+        g_prof.force = -1;
+        if (rc) return rc;
+        LAUNCH(PK_SAMPLE_SORT, k_unpack_sample, dim3(grid_of(P.m, 256, 4096)), dim3(256), 0, st,
+               (const uint64_t*)pk, (uint32_t*)a.s_ord, a.s_tag, (uint64_t)P.m);
+        LAUNCH_CHECK();
+        LAUNCH(PK_TREE, k_build_tree<KW>, dim3(grid_of(std::max<uint64_t>(P.m, P.p_eff), 256, 1024)), dim3(256), 0,
+               st, a, (const void*)a.s_ord, (const uint32_t*)a.s_tag, exp);
+        sample_done = true;
+      }
+    }
+    if (sample_done) {
+    } else if (l == 0 && P.lp.big_sample) {
       const uint32_t ch = sample_chunk(KW);
       LAUNCH(PK_SAMPLE_SORT, k_sample_chunk_sort<KW>, dim3((uint32_t)cdiv(P.m, ch)), dim3(NT), 0, st, a);
       LAUNCH_CHECK();

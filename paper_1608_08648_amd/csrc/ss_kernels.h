@@ -709,6 +709,25 @@ __global__ void __launch_bounds__(256) k_build_tree(LevelArgs a, const void* sor
   }
 }
 
+// A sample of 4-byte keys too large for the merge passes is sorted as
+// 64-bit keys (ord << 32) | tag, which order exactly as the records (key,
+// tag): pack before, unpack after.
+constexpr uint64_t SAMPLE_NESTED_MIN = 1ull << 20;
+
+__global__ void __launch_bounds__(256) k_pack_sample(const uint32_t* so, const uint32_t* stag, uint64_t* pk,
+                                                     uint64_t m) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (uint64_t)gridDim.x * 256)
+    pk[i] = ((uint64_t)so[i] << 32) | stag[i];
+}
+
+__global__ void __launch_bounds__(256) k_unpack_sample(const uint64_t* pk, uint32_t* so, uint32_t* stag, uint64_t m) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (uint64_t)gridDim.x * 256) {
+    const uint64_t v = pk[i];
+    so[i] = (uint32_t)(v >> 32);
+    stag[i] = (uint32_t)v;
+  }
+}
+
 // Regular sample (Alg. 1 steps 1-2) from blocks already sorted by (key,
 // in-block index): block k = [floor(k n/p), floor((k+1) n/p)); with
 // S = s*p and x = ceil(ceil(n/p)/S), record j of block k is the block's
