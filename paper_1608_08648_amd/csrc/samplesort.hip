@@ -157,6 +157,10 @@ uint32_t p_effective(uint64_t n, uint32_t p, uint32_t s, int mode) {
 // Tiles are whole multiples of 8192 keys (the split chunk and id block of
 // every key width).
 constexpr uint32_t TILE_UNIT = 8192;
+// capacity (LDS tree and counters) of the split kernels for a level whose
+// segments take up to p buckets: the smallest instantiated bound >= p
+uint32_t pmax_for(uint32_t p) { return p <= 256 ? 256 : (p <= 512 ? 512 : (p <= 1024 ? 1024 : 4096)); }
+
 uint32_t default_tile(uint32_t p) {
   uint64_t t = std::max<uint64_t>(65536, 16ull * p);
   return (uint32_t)(cdiv(t, TILE_UNIT) * TILE_UNIT);
@@ -200,7 +204,7 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
     lv.target = target;
     if (l == 0 && p0) {
       lv.p_cap = p0;
-      lv.pmax = p0 > 256 ? 4096 : 256;
+      lv.pmax = pmax_for(p0);
       lv.tile = tile_req ? (uint32_t)(cdiv(tile_req, TILE_UNIT) * TILE_UNIT) : default_tile(p0);
       lv.seg_cap = 1;
       lv.samp_cap = m0;
@@ -210,7 +214,7 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
       est = est_max0;
     } else {
       lv.p_cap = p_cap;
-      lv.pmax = p_cap > 256 ? 4096 : 256;
+      lv.pmax = pmax_for(p_cap);
       lv.tile = tile_req ? (uint32_t)(cdiv(tile_req, TILE_UNIT) * TILE_UNIT) : default_tile(p_cap);
       uint64_t sc = (l == 0) ? seg_cap0 : std::min<uint64_t>(P->lv[l - 1].bkt_cap, N / (Cpush + 1) + 1);
       sc = std::min<uint64_t>(sc, N / (Cpush + 1) + 1);
@@ -708,8 +712,12 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       }
     }
     const uint32_t tiles = (uint32_t)lv.tiles_cap;
-    if (lv.pmax > 256) LAUNCH(PK_CLASSIFY, (k_classify<KW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
-    else LAUNCH(PK_CLASSIFY, (k_classify<KW, 256>), dim3(tiles), dim3(NT), 0, st, a);
+    switch (lv.pmax) {
+      case 256: LAUNCH(PK_CLASSIFY, (k_classify<KW, 256>), dim3(tiles), dim3(NT), 0, st, a); break;
+      case 512: LAUNCH(PK_CLASSIFY, (k_classify<KW, 512>), dim3(tiles), dim3(NT), 0, st, a); break;
+      case 1024: LAUNCH(PK_CLASSIFY, (k_classify<KW, 1024>), dim3(tiles), dim3(NT), 0, st, a); break;
+      default: LAUNCH(PK_CLASSIFY, (k_classify<KW, 4096>), dim3(tiles), dim3(NT), 0, st, a); break;
+    }
     LAUNCH_CHECK();
     const uint32_t nb = (uint32_t)cdiv(std::max<uint64_t>(lv.hist_cap, 1), SCAN_BLOCK);
     const uint64_t* tot_dev = &a.ctl->total_hist;
@@ -720,8 +728,12 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
     LAUNCH_CHECK();
     if constexpr (VW == 0) {
       // keys only: equal keys are bit-identical, so placement order inside a bucket is free
-      if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter_keys<KW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
-      else LAUNCH(PK_SCATTER, (k_scatter_keys<KW, 256>), dim3(tiles), dim3(NT), 0, st, a);
+      switch (lv.pmax) {
+        case 256: LAUNCH(PK_SCATTER, (k_scatter_keys<KW, 256>), dim3(tiles), dim3(NT), 0, st, a); break;
+        case 512: LAUNCH(PK_SCATTER, (k_scatter_keys<KW, 512>), dim3(tiles), dim3(NT), 0, st, a); break;
+        case 1024: LAUNCH(PK_SCATTER, (k_scatter_keys<KW, 1024>), dim3(tiles), dim3(NT), 0, st, a); break;
+        default: LAUNCH(PK_SCATTER, (k_scatter_keys<KW, 4096>), dim3(tiles), dim3(NT), 0, st, a); break;
+      }
       LAUNCH_CHECK();
       LAUNCH(PK_BUCKET_SORT, (k_bucket_sort_keys<KW>), dim3((uint32_t)lv.bkt_cap), dim3(NT), 0, st, a, exp);
       LAUNCH_CHECK();
@@ -734,8 +746,12 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       }
       LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<KW>), dim3(gl), dim3(NT), 0, st, a, KW == 4 ? 1 : 0);
     } else {
-      if (lv.pmax > 256) LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 4096>), dim3(tiles), dim3(NT), 0, st, a);
-      else LAUNCH(PK_SCATTER, (k_scatter_pairs<KW, VW>), dim3(tiles), dim3(NT), 0, st, a);
+      switch (lv.pmax) {
+        case 256: LAUNCH(PK_SCATTER, (k_scatter_pairs<KW, VW>), dim3(tiles), dim3(NT), 0, st, a); break;
+        case 512: LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 512>), dim3(tiles), dim3(NT), 0, st, a); break;
+        case 1024: LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 1024>), dim3(tiles), dim3(NT), 0, st, a); break;
+        default: LAUNCH(PK_SCATTER, (k_scatter<KW, VW, 4096>), dim3(tiles), dim3(NT), 0, st, a); break;
+      }
       LAUNCH_CHECK();
       // stable slot sort; buckets too large or crowded go on to the radix /
       // next-level kernel

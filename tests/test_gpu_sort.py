@@ -235,3 +235,33 @@ def test_status_clean_after_sort():
     api.sort_keys(kd, prm, ws=w)
     msg = api.status(w)
     assert "0x4" not in msg
+
+
+@pytest.mark.parametrize("dtype,vt,p,flags", [
+    (np.int32, None, 512, 0),                      # one-pass split, 512-bucket kernels
+    (np.int32, None, 1024, N.SS_F_NO_WIDE),        # 1024-bucket kernels
+    (np.uint64, None, 512, 0),
+    (np.uint64, None, 1024, 0),
+    (np.int32, "b64", 512, 0),                     # stable split with payload, 512 buckets
+    (np.uint64, "b32", 1024, 0),                   # 1024 buckets
+    (np.float32, "b32", 2048, 0),                  # 4096-bucket kernels
+])
+def test_split_bucket_bounds(dtype, vt, p, flags):
+    """The split kernels are built for at most 256, 512, 1024 or 4096
+    buckets; each level takes the smallest bound >= its p.  2^21 + 99 keys
+    with duplicates: bucket counts equal the oracle's, keys (and payloads,
+    stable) bit-exact."""
+    n = (1 << 21) + 99
+    keys = rand_keys(n, dtype, 1000 + p)
+    kd, kt = to_dev(keys)
+    note(f"split bound {np.dtype(dtype)} vt={vt} p={p} flags={flags}")
+    if vt is None:
+        _stage_check(keys, p, 8, 0, 77, flags)
+        return
+    vdt = np.uint32 if vt == "b32" else np.uint64
+    vals = np.random.default_rng(p).integers(0, 2**31, n).astype(vdt)
+    vd, _ = to_dev(vals)
+    perm = oracle.stable_perm(keys)
+    ko, vo = api.sort_pairs(kd, vd, prm=api.params(p=p, s=8, seed=77, flags=flags), key_type=kt)
+    np.testing.assert_array_equal(to_host(ko, keys.dtype).view(np.uint8), keys[perm].view(np.uint8))
+    np.testing.assert_array_equal(to_host(vo, vdt), vals[perm])
