@@ -202,17 +202,18 @@ __device__ __forceinline__ void wide_load(uint32_t (&k)[U], const uint32_t* src,
 
 struct WideCountLds {
   uint32_t sk[WIDE_PMAX];        // sorted splitter keys (rank 1..p-1)
-  uint32_t st[WIDE_PMAX];        // their tags
   uint32_t cells[WIDE_CELLS];
-  uint32_t cnt[WIDE_PMAX];       // non-tie keys per fine bucket
+  uint32_t cnt[WIDE_PMAX / 2];   // non-tie keys per fine bucket, two 16-bit counts per word
   uint32_t ties[WIDE_PMAX];      // tie-low | tie-high << 16 (a tile holds < 2^16 keys)
   uint32_t csum[WIDE_P1];
   WideHdr h;
 };
 
 // Per tile: classify every key (step 4) and count.  Runs of equal (kind,
-// bucket) in a thread's keys are added to the LDS counters at once.
-__global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
+// bucket) in a thread's keys are added to the LDS counters at once.  (Six
+// waves per SIMD, three work-groups per CU: the LDS holds 16-bit counts and
+// no tags, the compiler keeps to 80 VGPRs.)
+__global__ void __launch_bounds__(NT, 6) k_wide_count(WideArgs w) {
   __shared__ WideCountLds sm;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= w.W) return;
@@ -222,12 +223,12 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
   const uint32_t* src = (const uint32_t*)w.src;
   uint32_t nk[WIDE_U];
   wide_load(nk, src, t0, t1);
+  const uint32_t* stg = w.stags;   // tags: only tie keys read them (from L2)
   for (uint32_t k = t; k < p; k += NT) {
     sm.sk[k] = w.skeys[k];
-    sm.st[k] = w.stags[k];
-    sm.cnt[k] = 0;
     sm.ties[k] = 0;
   }
+  for (uint32_t k = t; k < p / 2; k += NT) sm.cnt[k] = 0;
   const WideHdr h = *w.hdr;
   for (uint32_t j = t; j < h.ncell; j += NT) sm.cells[j] = w.cells[j];
   if (t < (int)WIDE_P1) sm.csum[t] = 0;
@@ -237,7 +238,7 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
   auto flush = [&]() {
     if (!run) return;
     const uint32_t kind = cur >> 16, b = cur & 0xFFFFu;
-    if (kind == 0) atomicAdd(&sm.cnt[b], run);
+    if (kind == 0) atomicAdd(&sm.cnt[b >> 1], run << (16 * (b & 1)));
     else atomicAdd(&sm.ties[b], kind == 1 ? run : run << 16);
   };
   for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_CH) {
@@ -258,8 +259,8 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
           const uint32_t hb = hint;
           bool hit = false;
           if (hb != ~0u && hb + 1 >= lo) {
-            const bool above = hb == 0 || sm.sk[hb] < k || (sm.sk[hb] == k && sm.st[hb] < i);
-            const bool below = hb + 1 == p || k < sm.sk[hb + 1] || (k == sm.sk[hb + 1] && i < sm.st[hb + 1]);
+            const bool above = hb == 0 || sm.sk[hb] < k || (sm.sk[hb] == k && stg[hb] < i);
+            const bool below = hb + 1 == p || k < sm.sk[hb + 1] || (k == sm.sk[hb + 1] && i < stg[hb + 1]);
             hit = above && below;
           }
           if (hit) {
@@ -268,7 +269,7 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
           } else {
             // every splitter with this key lies in the key's cell: [lo, up]
             const uint32_t up = sm.cells[(k - h.kmin) >> h.sh] >> 16;
-            b = wide_tie_bucket(sm.sk, sm.st, p, lo, up, k, i, kind);
+            b = wide_tie_bucket(sm.sk, stg, p, lo, up, k, i, kind);
           }
           hint = b;
         }
@@ -286,7 +287,7 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
   __syncthreads();
   const uint32_t R = w.W + 2;
   for (uint32_t b = t; b < p; b += NT) {
-    w.hf[(uint64_t)b * R + 1 + tile] = sm.cnt[b];
+    w.hf[(uint64_t)b * R + 1 + tile] = (sm.cnt[b >> 1] >> (16 * (b & 1))) & 0xFFFFu;
     const uint32_t tl = sm.ties[b] & 0xFFFFu, th = sm.ties[b] >> 16;
     if (tl) atomicAdd(&w.hf[(uint64_t)b * R], tl);
     if (th) atomicAdd(&w.hf[(uint64_t)b * R + R - 1], th);
@@ -296,7 +297,10 @@ __global__ void __launch_bounds__(NT) k_wide_count(WideArgs w) {
   {
     const uint32_t K = p / NT, P2 = p >> WIDE_LG1;
     uint32_t s = 0;
-    for (uint32_t j = 0; j < K; j++) s += sm.cnt[t * K + j];
+    for (uint32_t j = 0; j < K; j++) {
+      const uint32_t b = t * K + j;
+      s += (sm.cnt[b >> 1] >> (16 * (b & 1))) & 0xFFFFu;
+    }
     if (s) atomicAdd(&sm.csum[(t * K) / P2], s);
   }
   __syncthreads();
