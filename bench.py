@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # on; "traffic" is null for anything else.
 MEASURED_TRAFFIC = {
     ("bucket_sort", 26, 4096, 16, "random", "uniform"): {
-        "src_sha256_16": "5c66f3d3cafd8347",
-        "bytes_per_launch": 542508870,   # k_wide_bucket: FETCH 133,650 KiB x 2 + WRITE 262,494 KiB
+        "src_sha256_16": "4676f316578d7c38",
+        "bytes_per_launch": 548227142,   # k_wide_bucket: FETCH 136,442 KiB x 2 + WRITE 262,494 KiB
     },
 }
 
