@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(NT) k_bucket_leftover_pairs(LevelArgs a) {
 // wave's offset inside each bucket's run, so every key's position follows
 // input order (stability); the chunk is grouped by bucket in LDS and every
 // bucket's run is written contiguously.
-constexpr int PAIRS_R = 8;                   // rows per wave in a chunk
+constexpr int PAIRS_R = 6;                   // rows per wave in a chunk
 constexpr int PAIRS_CH = PAIRS_R * NT;       // keys per chunk
 constexpr int PAIRS_WAVES = NT / WAVE;
 
@@ -260,8 +260,10 @@ struct ScatterPairsLds {
   alignas(8) uint32_t red[32];
 };
 
+// (six waves per SIMD: three work-groups per CU for 8-byte keys with a
+// 4-byte payload, whose chunk takes 53 KB of LDS)
 template <int KW, int VW>
-__global__ void __launch_bounds__(NT) k_scatter_pairs(LevelArgs a) {
+__global__ void __launch_bounds__(NT, 6) k_scatter_pairs(LevelArgs a) {
   using KT = typename KeyOf<KW>::T;
   using VT = typename ValOf<VW>::T;
   constexpr int R = PAIRS_R;
