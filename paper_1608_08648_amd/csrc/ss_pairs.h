@@ -241,8 +241,13 @@ __global__ void __launch_bounds__(NT) k_bucket_leftover_pairs(LevelArgs a) {
 // wave's offset inside each bucket's run, so every key's position follows
 // input order (stability); the chunk is grouped by bucket in LDS and every
 // bucket's run is written contiguously.
-constexpr int PAIRS_R = 6;                   // rows per wave in a chunk
-constexpr int PAIRS_CH = PAIRS_R * NT;       // keys per chunk
+// rows per wave in a chunk: 6 for 8-byte keys (3072 pairs, whose LDS then
+// allows three work-groups per CU), 8 for 4-byte keys (measured faster)
+template <int KW> struct PairsChunk {
+  static constexpr int R = KW == 8 ? 6 : 8;
+  static constexpr int CH = R * NT;          // keys per chunk
+  static constexpr int WPE = KW == 8 ? 6 : 1;   // waves per SIMD the kernel is built for (1: no bound)
+};
 constexpr int PAIRS_WAVES = NT / WAVE;
 
 template <int KW, int VW>
@@ -254,19 +259,20 @@ struct ScatterPairsLds {
   uint32_t gofs[256];                        // before the first chunk: in-segment position of each
                                              // bucket's run; then that position - chunk position
   uint32_t tot[256];                         // keys of each bucket in the chunk
-  KT sk[PAIRS_CH];
-  VT sv[PAIRS_CH];
-  uint8_t sb[PAIRS_CH];
+  KT sk[PairsChunk<KW>::CH];
+  VT sv[PairsChunk<KW>::CH];
+  uint8_t sb[PairsChunk<KW>::CH];
   alignas(8) uint32_t red[32];
 };
 
-// (six waves per SIMD: three work-groups per CU for 8-byte keys with a
-// 4-byte payload, whose chunk takes 53 KB of LDS)
+// (8-byte keys: six waves per SIMD, three work-groups per CU with a 4-byte
+// payload, whose chunk takes 53 KB of LDS)
 template <int KW, int VW>
-__global__ void __launch_bounds__(NT, 6) k_scatter_pairs(LevelArgs a) {
+__global__ void __launch_bounds__(NT, PairsChunk<KW>::WPE) k_scatter_pairs(LevelArgs a) {
   using KT = typename KeyOf<KW>::T;
   using VT = typename ValOf<VW>::T;
-  constexpr int R = PAIRS_R;
+  constexpr int R = PairsChunk<KW>::R;
+  constexpr int PAIRS_CH = PairsChunk<KW>::CH;
   __shared__ ScatterPairsLds<KW, VW> sm;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   const LevelCtl c = *a.ctl;
