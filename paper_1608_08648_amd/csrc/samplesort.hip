@@ -47,12 +47,12 @@ int fail(int code, const char* fmt, ...) {
 enum ProfKind {
   PK_INIT, PK_PLAN, PK_SAMPLE, PK_SAMPLE_SORT, PK_SAMPLE_MERGE, PK_TREE, PK_CLASSIFY, PK_SCAN, PK_SCATTER,
   PK_BUCKET_SORT, PK_BUCKET_LEFT, PK_SMALL_SORT, PK_BLOCK_SORT_REGULAR, PK_GRAD, PK_SPLIT_COARSE, PK_SPLIT_FINE,
-  PK_SF_SEARCH, PK_SF_GATHER, PK_COUNT
+  PK_SF_SEARCH, PK_SF_GATHER, PK_WIDEN, PK_COUNT
 };
 const char* const PROF_NAMES[PK_COUNT] = {
     "init", "plan", "sample", "sample_sort", "sample_merge", "tree", "classify", "scan", "scatter",
     "bucket_sort", "bucket_leftover", "small_sort", "regular_blocks", "scatter_grad", "split_coarse",
-    "split_fine", "sf_search", "sf_gather"};
+    "split_fine", "sf_search", "sf_gather", "widen"};
 
 struct Prof {
   bool on = false;
@@ -283,6 +283,9 @@ struct Plan {
   // a large sample of 4-byte keys: packed records and the nested sort that orders them
   Plan* nested_s = nullptr;
   size_t o_spack = 0, o_nested_s = 0;
+  // a 64-bit index payload sorted as a 32-bit one, then widened
+  bool widen = false;
+  size_t o_widen = 0;
   size_t bytes = 0;
   ~Plan() {
     delete nested;
@@ -308,7 +311,9 @@ int check_params(const ss_params* prm, ss_params* out) {
 int plan_segmented(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, const Types& ty, const ss_params& prm,
                    bool user_params);
 
-int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
+int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm);
+
+int plan_single_t(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   P->ty = ty;
   P->n = n;
   P->prm = prm;
@@ -426,7 +431,7 @@ int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   return SS_OK;
 }
 
-int plan_segmented(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, const Types& ty, const ss_params& prm,
+int plan_segmented_t(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, const Types& ty, const ss_params& prm,
                    bool user_params) {
   P->ty = ty;
   P->n = total;
@@ -468,6 +473,41 @@ bool overlap_partial(const void* a, size_t an, const void* b, size_t bn) {
 }
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+// A 64-bit index payload (< 2^32 within an array or a segment) is sorted as
+// a 32-bit one into the workspace and widened once at the end: every pass
+// then moves 4 bytes less per element.
+Types narrow_index(const Types& ty) {
+  Types t = ty;
+  t.VW = 4;
+  t.vt = SS_V_IOTA32;
+  return t;
+}
+
+void add_widen(Plan* P, uint64_t n) {
+  Layout L;
+  L.cur = P->bytes;
+  P->o_widen = L.take(4 * std::max<uint64_t>(n, 1));
+  P->bytes = L.cur;
+  P->widen = true;
+}
+
+int plan_single(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
+  if (!(ty.iota && ty.VW == 8)) return plan_single_t(P, n, ty, prm);
+  const int rc = plan_single_t(P, n, narrow_index(ty), prm);
+  if (rc) return rc;
+  add_widen(P, n);
+  return SS_OK;
+}
+
+int plan_segmented(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, const Types& ty, const ss_params& prm,
+                   bool user_params) {
+  if (!(ty.iota && ty.VW == 8)) return plan_segmented_t(P, total, nseg, maxlen, ty, prm, user_params);
+  const int rc = plan_segmented_t(P, total, nseg, maxlen, narrow_index(ty), prm, user_params);
+  if (rc) return rc;
+  add_widen(P, total);
+  return SS_OK;
+}
 
 LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void* vin, void* out, void* vout) {
   const LevelPlan& lv = P.lp.lv[l];
@@ -823,7 +863,7 @@ int dispatch_single(const Plan& P, char* ws, const void* in, const void* vin, vo
   return run_single<KW, VW>(P, ws, in, vin, out, vout, st);
 }
 
-int run_single_any(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st) {
+int run_single_t(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st) {
   const int KW = P.ty.KW, VW = P.ty.VW;
   if (KW == 4 && VW == 0) return dispatch_single<4, 0>(P, ws, in, vin, out, vout, st);
   if (KW == 4 && VW == 4) return dispatch_single<4, 4>(P, ws, in, vin, out, vout, st);
@@ -833,8 +873,8 @@ int run_single_any(const Plan& P, char* ws, const void* in, const void* vin, voi
   return dispatch_single<8, 8>(P, ws, in, vin, out, vout, st);
 }
 
-int run_segmented_any(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout,
-                      const int64_t* off, hipStream_t st) {
+int run_segmented_t(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout,
+                    const int64_t* off, hipStream_t st) {
   const int KW = P.ty.KW, VW = P.ty.VW;
   if (KW == 4 && VW == 0) return run_segmented<4, 0>(P, ws, in, vin, out, vout, off, st);
   if (KW == 4 && VW == 4) return run_segmented<4, 4>(P, ws, in, vin, out, vout, off, st);
@@ -842,6 +882,30 @@ int run_segmented_any(const Plan& P, char* ws, const void* in, const void* vin, 
   if (KW == 8 && VW == 0) return run_segmented<8, 0>(P, ws, in, vin, out, vout, off, st);
   if (KW == 8 && VW == 4) return run_segmented<8, 4>(P, ws, in, vin, out, vout, off, st);
   return run_segmented<8, 8>(P, ws, in, vin, out, vout, off, st);
+}
+
+int run_single_any(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout, hipStream_t st) {
+  if (!P.widen) return run_single_t(P, ws, in, vin, out, vout, st);
+  uint32_t* v32 = (uint32_t*)(ws + P.o_widen);
+  const int rc = run_single_t(P, ws, in, vin, out, v32, st);
+  if (rc) return rc;
+  LAUNCH(PK_WIDEN, k_widen_index, dim3(grid_of(P.n, 256, 8192)), dim3(256), 0, st, (const uint32_t*)v32,
+         (int64_t*)vout, (const int64_t*)nullptr, (uint64_t)0, (uint64_t)P.n);
+  LAUNCH_CHECK();
+  return SS_OK;
+}
+
+int run_segmented_any(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout,
+                      const int64_t* off, hipStream_t st) {
+  if (!P.widen) return run_segmented_t(P, ws, in, vin, out, vout, off, st);
+  uint32_t* v32 = (uint32_t*)(ws + P.o_widen);
+  const int rc = run_segmented_t(P, ws, in, vin, out, v32, off, st);
+  if (rc) return rc;
+  // (only [off[0], off[nseg]) holds sorted segments)
+  LAUNCH(PK_WIDEN, k_widen_index, dim3(grid_of(P.n, 256, 8192)), dim3(256), 0, st, (const uint32_t*)v32,
+         (int64_t*)vout, off, (uint64_t)P.nseg, (uint64_t)P.n);
+  LAUNCH_CHECK();
+  return SS_OK;
 }
 
 int check_ws(const Plan& P, const void* ws, size_t ws_bytes) {

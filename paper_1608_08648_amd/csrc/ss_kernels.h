@@ -709,6 +709,22 @@ __global__ void __launch_bounds__(256) k_build_tree(LevelArgs a, const void* sor
   }
 }
 
+// Widening of a 32-bit index payload into the caller's 64-bit one: all of
+// [0, n) for an array; for segments, [off[0], off[nseg]) (off == nullptr:
+// the whole range).
+__global__ void __launch_bounds__(256) k_widen_index(const uint32_t* v32, int64_t* v64, const int64_t* off,
+                                                     uint64_t nseg, uint64_t n) {
+  uint64_t b = 0, e = n;
+  if (off) {
+    const int64_t ob = off[0], oe = off[nseg];
+    b = ob < 0 ? 0 : (uint64_t)ob;
+    e = oe < ob ? b : (uint64_t)oe;
+    if (e > n) e = n;
+  }
+  for (uint64_t i = b + (uint64_t)blockIdx.x * 256 + threadIdx.x; i < e; i += (uint64_t)gridDim.x * 256)
+    v64[i] = (int64_t)v32[i];
+}
+
 // A sample of 4-byte keys too large for the merge passes is sorted as
 // 64-bit keys (ord << 32) | tag, which order exactly as the records (key,
 // tag): pack before, unpack after.

@@ -265,3 +265,34 @@ def test_split_bucket_bounds(dtype, vt, p, flags):
     ko, vo = api.sort_pairs(kd, vd, prm=api.params(p=p, s=8, seed=77, flags=flags), key_type=kt)
     np.testing.assert_array_equal(to_host(ko, keys.dtype).view(np.uint8), keys[perm].view(np.uint8))
     np.testing.assert_array_equal(to_host(vo, vdt), vals[perm])
+
+
+def test_int64_index_sorted_narrow_and_widened():
+    """A 64-bit index payload (IOTA64) is sorted as a 32-bit one and widened
+    at the end.  Single array: the index equals the oracle's stable
+    permutation.  Segments starting at offset 7 (empty ones included): the
+    in-segment indices equal the oracle's, and the caller's output outside
+    [offsets[0], offsets[-1]) keeps its contents."""
+    n = (1 << 20) + 5
+    keys = rand_keys(n, np.int32, 91)
+    kd = torch.from_numpy(keys).cuda()
+    note("iota64 single")
+    ko, vo = api.sort_pairs(kd, iota="int64", prm=api.params(p=256, s=8))
+    assert vo.dtype == torch.int64
+    perm = oracle.stable_perm(keys)
+    np.testing.assert_array_equal(vo.cpu().numpy(), perm.astype(np.int64))
+    np.testing.assert_array_equal(ko.cpu().numpy(), keys[perm])
+    sizes = np.array([0, 9, 0, 40000, 1, 0, 300000, 3, 0], dtype=np.int64)
+    off = np.concatenate([[7], 7 + np.cumsum(sizes)]).astype(np.int64)
+    total = int(off[-1]) + 11
+    keys = rand_keys(total, np.float32, 92)
+    kd = torch.from_numpy(keys).cuda()
+    od = torch.from_numpy(off).cuda()
+    vals_out = torch.full((total,), -7, dtype=torch.int64, device="cuda")
+    note("iota64 segmented")
+    ko, vo = api.segmented_sort(kd, od, iota="int64", vals_out=vals_out, total=total,
+                                max_len=int(sizes.max()))
+    got = vo.cpu().numpy()
+    assert np.all(got[:7] == -7) and np.all(got[int(off[-1]):] == -7)
+    want = oracle.segmented_perm(keys[:int(off[-1])], off).astype(np.int64)
+    np.testing.assert_array_equal(got[7:int(off[-1])], want[7:])
