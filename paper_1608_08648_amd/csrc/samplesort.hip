@@ -622,7 +622,7 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   const uint64_t nf = (uint64_t)w.p * (w.W + 2) + 1, na = (uint64_t)WIDE_P1 * w.W + 1;
   uint32_t* pf = (uint32_t*)(ws + P.o_whf_part);
   uint32_t* pa = (uint32_t*)(ws + P.o_wha_part);
-  LAUNCH(PK_TREE, k_wide_table, dim3(1), dim3(NT), 0, st, w);
+  LAUNCH(PK_TREE, k_wide_table, dim3(WIDE_TABLE_WG), dim3(NT), 0, st, w);
   LAUNCH(PK_CLASSIFY, k_wide_count, dim3(w.W), dim3(NT), 0, st, w);
   LAUNCH_CHECK();
   const uint32_t nbf = (uint32_t)cdiv(nf, SCAN_BLOCK), nba = (uint32_t)cdiv(na, SCAN_BLOCK);

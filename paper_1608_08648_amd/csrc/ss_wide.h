@@ -85,21 +85,25 @@ struct WideArgs {
 // / cells of them for evenly spread keys) finds the count.
 constexpr int WIDE_CELL_BITS = 11;
 constexpr int WIDE_CELLS = 1 << WIDE_CELL_BITS;
+constexpr int WIDE_TABLE_WG = 8;                 // work-groups building the table
 
 // One work-group: the sorted splitters (rank r in [1, p): key and tag) from
 // the Eytzinger tree, and the cell table.
+// (every work-group of the launch builds the sorted keys in LDS and takes
+// its share of the tie entries and the cells; work-group 0 writes the rest)
 __global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
   __shared__ uint32_t sk[WIDE_PMAX];
   const uint32_t p = w.p;
+  const uint32_t g0 = blockIdx.x * NT + threadIdx.x, gs = gridDim.x * NT;
   // tie entries and the trailing totals of both count arrays start at zero
   // (the count kernel adds to them; it writes every other entry)
   {
     const uint32_t R = w.W + 2;
-    for (uint32_t b = threadIdx.x; b < p; b += NT) {
+    for (uint32_t b = g0; b < p; b += gs) {
       w.hf[(uint64_t)b * R] = 0;
       w.hf[(uint64_t)b * R + R - 1] = 0;
     }
-    if (threadIdx.x == 0) {
+    if (g0 == 0) {
       w.hf[(uint64_t)p * R] = 0;
       w.ha[(uint64_t)WIDE_P1 * w.W] = 0;
     }
@@ -109,8 +113,10 @@ __global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
     const uint32_t k = (1u << (w.lgp - 1 - z)) + (r >> (z + 1));
     const uint64_t nd = w.tree[k];
     sk[r] = (uint32_t)(nd >> 32);
-    w.skeys[r] = (uint32_t)(nd >> 32);
-    w.stags[r] = (uint32_t)nd;
+    if (blockIdx.x == 0) {
+      w.skeys[r] = (uint32_t)(nd >> 32);
+      w.stags[r] = (uint32_t)nd;
+    }
   }
   __syncthreads();
   const uint32_t kmin = sk[1], kmax = sk[p - 1];
@@ -128,8 +134,8 @@ __global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
     }
     return a - 1;
   };
-  for (uint32_t j = threadIdx.x; j < ncell; j += NT) w.cells[j] = L(j) | (L(j + 1) << 16);
-  if (threadIdx.x == 0) *w.hdr = WideHdr{kmin, kmax, sh, ncell};
+  for (uint32_t j = g0; j < ncell; j += gs) w.cells[j] = L(j) | (L(j + 1) << 16);
+  if (g0 == 0) *w.hdr = WideHdr{kmin, kmax, sh, ncell};
 }
 
 // Search of one key among the candidates of its cell, on the key alone:
