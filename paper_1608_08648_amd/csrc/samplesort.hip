@@ -276,6 +276,7 @@ struct Plan {
   bool wide = false;
   uint32_t wide_W = 0;
   size_t o_whf = 0, o_whf_part = 0, o_wha = 0, o_wha_part = 0, o_wkeys = 0, o_wtags = 0, o_wcells = 0, o_whdr = 0;
+  size_t o_wcb = 0;        // coarse region of every key
   size_t o_tmp2 = 0;       // wide split with input == output: a second copy
   // sort-first organisation: sorted blocks (o_regk, o_regi), the run table and the buckets
   bool sortfirst = false;
@@ -380,6 +381,7 @@ int plan_single_t(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
     P->o_wtags = L.take(4 * (size_t)p);
     P->o_wcells = L.take(4 * (size_t)WIDE_CELLS);
     P->o_whdr = L.take(sizeof(WideHdr));
+    P->o_wcb = L.take(n);
   }
   // (the wide split's bucket sort takes any size in rounds; a level below
   // pays once buckets would need many rounds)
@@ -613,6 +615,7 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   w.stags = (uint32_t*)(ws + P.o_wtags);
   w.cells = (uint32_t*)(ws + P.o_wcells);
   w.hdr = (WideHdr*)(ws + P.o_whdr);
+  w.cb = (uint8_t*)(ws + P.o_wcb);
   w.kin = P.ty.kind;
   w.kout = P.ty.kind;
   // the leftover kernel sorts fine -> out (the stage is free scratch by then)

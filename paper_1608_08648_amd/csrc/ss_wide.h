@@ -9,10 +9,12 @@
 //   k_wide_table    sorted splitter keys and a cell table over their range
 //   k_wide_count    per tile: the fine bucket of every key (cell table and a
 //                   short binary search), non-tie counts per (bucket, tile),
-//                   tie counts per bucket
+//                   tie counts per bucket; one byte per key for the first
+//                   pass: its coarse region, or 0xFF for a tie key
 //   k_scan_*        exclusive scans of both count arrays
 //   k_wide_split_a  per tile: non-tie keys to P1 = 64 coarse regions (a
-//                   coarse bucket is P2 = p / 64 consecutive fine buckets)
+//                   coarse bucket is P2 = p / 64 consecutive fine buckets),
+//                   read from the classification's bytes
 //   k_wide_split_b  per piece of a coarse region: keys to their fine buckets
 //                   (walk of the region's own subtree on the key alone)
 //   k_wide_bucket   per fine bucket: fill the tie runs, sort the rest in LDS
@@ -44,7 +46,8 @@ constexpr uint32_t WIDE_P1 = 1u << WIDE_LG1;   // coarse buckets
 constexpr int WIDE_PMAX = 4096;
 constexpr int WIDE_U = 16;                     // keys per thread per chunk
 constexpr int WIDE_CH = WIDE_U * NT;
-constexpr int WIDE_UA = 8;                     // keys per thread per chunk of the first pass (LDS)
+constexpr int WIDE_UA = 8;                      // keys per thread per chunk of the second pass (LDS)
+constexpr int WIDE_UA1 = 16;                    // keys per thread per chunk of the first pass (LDS)
 constexpr uint32_t WIDE_TILE = 7 * WIDE_U * 512; // keys per input tile (< 2^16: 16-bit tie counters)
 constexpr uint32_t WIDE_TB = 65536;            // nominal keys per piece of the second pass
 // bucket sort of the wide split: 1024 threads, 30720 keys per round in LDS
@@ -72,6 +75,7 @@ struct WideArgs {
   uint32_t* stags;        // their tags
   uint32_t* cells;        // cell table
   WideHdr* hdr;
+  uint8_t* cb;            // per key: its coarse region, 0xFF for a tie key (not moved)
   uint32_t n, p, lgp, W, tile;
   int kin, kout;
 };
@@ -206,6 +210,17 @@ __device__ __forceinline__ void wide_load(uint32_t (&k)[U], const uint32_t* src,
   }
 }
 
+// coarse-region bytes of one chunk (0xFF past the end)
+template <int U>
+__device__ __forceinline__ void wide_load_b(uint32_t (&b)[U], const uint8_t* cb, uint32_t i0, uint32_t end) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < U; u++) {
+    const uint32_t i = i0 + u * NT + t;
+    b[u] = i < end ? (uint32_t)cb[i] : 0xFFu;
+  }
+}
+
 struct WideCountLds {
   uint32_t sk[WIDE_PMAX];        // sorted splitter keys (rank 1..p-1)
   uint32_t cells[WIDE_CELLS];
@@ -224,7 +239,7 @@ __global__ void __launch_bounds__(NT, 6) k_wide_count(WideArgs w) {
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= w.W) return;
   const int t = threadIdx.x;
-  const uint32_t p = w.p;
+  const uint32_t p = w.p, lg2 = w.lgp - WIDE_LG1;
   const uint32_t t0 = tile * w.tile, t1 = min(t0 + w.tile, w.n);
   const uint32_t* src = (const uint32_t*)w.src;
   uint32_t nk[WIDE_U];
@@ -258,6 +273,7 @@ __global__ void __launch_bounds__(NT, 6) k_wide_count(WideArgs w) {
       if (i < t1) {
         bool tie;
         const uint32_t lo = wide_lower(sm.sk, sm.cells, h, p, key[u], tie);
+        w.cb[i] = tie ? (uint8_t)0xFFu : (uint8_t)((lo - 1) >> lg2);
         uint32_t b = lo - 1, kind = 0;
         if (tie) {
           // equal keys in input order mostly share a bucket: try the last one
@@ -385,27 +401,23 @@ __device__ __forceinline__ void wide_group_write(WideSplitLds<NB, U>& sm, const 
 }
 
 struct WideALds {
-  uint32_t sk[WIDE_PMAX];
-  uint32_t cells[WIDE_CELLS];
-  WideSplitLds<WIDE_P1, WIDE_UA> g;
+  WideSplitLds<WIDE_P1, WIDE_UA1> g;
 };
 
 // First pass, per input tile: non-tie keys to their coarse region, in runs.
-// (For a non-tie key the count of splitters below it is decided by the key
-// alone; tie keys stay where they are.)
+// The region comes from the classification's byte per key (the fine bucket's
+// top bits; 0xFF: a tie key, which stays where it is), so the keys are not
+// searched again.
 __global__ void __launch_bounds__(NT) k_wide_split_a(WideArgs w) {
   __shared__ WideALds sm;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= w.W) return;
   const int t = threadIdx.x;
-  const uint32_t p = w.p, lg2 = w.lgp - WIDE_LG1;
   const uint32_t t0 = tile * w.tile, t1 = min(t0 + w.tile, w.n);
   const uint32_t* src = (const uint32_t*)w.src;
-  uint32_t nk[WIDE_UA];
+  uint32_t nk[WIDE_UA1], nb[WIDE_UA1];
   wide_load(nk, src, t0, t1);
-  for (uint32_t k = t; k < p; k += NT) sm.sk[k] = w.skeys[k];
-  const WideHdr h = *w.hdr;
-  for (uint32_t j = t; j < h.ncell; j += NT) sm.cells[j] = w.cells[j];
+  wide_load_b(nb, w.cb, t0, t1);
   if (t < (int)WIDE_P1) {
     sm.g.gofs[t] = w.ha[(uint64_t)t * w.W + tile];
     sm.g.cur[0][t] = 0;
@@ -413,16 +425,15 @@ __global__ void __launch_bounds__(NT) k_wide_split_a(WideArgs w) {
   }
   __syncthreads();
   int x = 0;
-  for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_UA * NT, x ^= 1) {
-    uint32_t key[WIDE_UA], c[WIDE_UA];
+  for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_UA1 * NT, x ^= 1) {
+    uint32_t key[WIDE_UA1], c[WIDE_UA1];
 #pragma unroll
-    for (int u = 0; u < WIDE_UA; u++) key[u] = to_ord(nk[u], w.kin);
-    if (i0 + WIDE_UA * NT < t1) wide_load(nk, src, i0 + WIDE_UA * NT, t1);
+    for (int u = 0; u < WIDE_UA1; u++) key[u] = to_ord(nk[u], w.kin);
 #pragma unroll
-    for (int u = 0; u < WIDE_UA; u++) {
-      bool tie;
-      const uint32_t lo = wide_lower(sm.sk, sm.cells, h, p, key[u], tie);
-      c[u] = (i0 + u * NT + t < t1 && !tie) ? ((lo - 1) >> lg2) : ~0u;
+    for (int u = 0; u < WIDE_UA1; u++) c[u] = (i0 + u * NT + t < t1 && nb[u] != 0xFFu) ? nb[u] : ~0u;
+    if (i0 + WIDE_UA1 * NT < t1) {
+      wide_load(nk, src, i0 + WIDE_UA1 * NT, t1);
+      wide_load_b(nb, w.cb, i0 + WIDE_UA1 * NT, t1);
     }
     wide_group_write(sm.g, key, c, w.stage, x, i0 == t0);
   }
