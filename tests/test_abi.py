@@ -168,3 +168,21 @@ def test_segmented_workspace():
     small = out.value
     assert L.ss_segmented_workspace_size(20000 * 100, 20000, 2**20, N.SS_I32, 0, None, ctypes.byref(out)) == 0
     assert out.value > small
+
+
+def test_int64_index_payload_planned_narrow():
+    """A 64-bit index payload (IOTA64) is planned as a 32-bit one plus a
+    buffer of n 32-bit indices that is widened at the end: its workspace is
+    the IOTA32 plan's plus 4n bytes (rounded to the 256-byte alignment), for
+    single arrays and for segments."""
+    for n, p in [(2**20 + 5, 256), (2**26, 4096), (1000, 64)]:
+        rc32, b32 = _ws(n, N.SS_F32, N.SS_V_IOTA32, p=p)
+        rc64, b64 = _ws(n, N.SS_F32, N.SS_V_IOTA64, p=p)
+        assert rc32 == 0 and rc64 == 0
+        assert b64 - b32 == ((b32 + 255) // 256 * 256 - b32) + 4 * n
+    L = N.lib()
+    out32, out64 = ctypes.c_size_t(), ctypes.c_size_t()
+    total, nseg, maxlen = 64 * 2**18, 64, 2**18
+    assert L.ss_segmented_workspace_size(total, nseg, maxlen, N.SS_F32, N.SS_V_IOTA32, None, ctypes.byref(out32)) == 0
+    assert L.ss_segmented_workspace_size(total, nseg, maxlen, N.SS_F32, N.SS_V_IOTA64, None, ctypes.byref(out64)) == 0
+    assert out64.value - out32.value == ((out32.value + 255) // 256 * 256 - out32.value) + 4 * total
