@@ -44,7 +44,10 @@ enum { SS_U32 = 0, SS_I32 = 1, SS_F32 = 2, SS_U64 = 3, SS_I64 = 4, SS_F64 = 5 };
 /* payload types: a payload is moved bit-exactly with its key.
  * SS_V_IOTA32 / SS_V_IOTA64: no payload is read (vals_in must be NULL); the
  * payload of each key is its index within its array or segment, written as
- * uint32 / int64, i.e. the stable sorting permutation. */
+ * uint32 / int64, i.e. the stable sorting permutation.  SS_V_IOTA64 is
+ * sorted as a 32-bit index in the workspace (4 bytes per element more) and
+ * widened into vals_out at the end; vals_out outside a segmented sort's
+ * [offsets[0], offsets[num_segments]) is not written. */
 enum { SS_V_NONE = 0, SS_V_B32 = 1, SS_V_B64 = 2, SS_V_IOTA32 = 3, SS_V_IOTA64 = 4 };
 
 /* sampling rule */
