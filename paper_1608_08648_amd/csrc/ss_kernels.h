@@ -1215,9 +1215,23 @@ __device__ __forceinline__ void slot_rank_write(const typename KeyOf<KW>::T* pla
     uint32_t s0, s1;
     bounds(k, s0, s1);
     uint32_t rank = 0;
-    for (uint32_t j = s0; j < s1; j++) {
-      const KT o = placed[j];
-      rank += (o < k || (o == k && j < i)) ? 1u : 0u;
+    if constexpr (KW == 4) {
+      // (key, position) as one 64-bit number: smaller, or equal and placed
+      // earlier, is one compare; two keys of the slot per step, the second
+      // read clamped into the slot and not counted past its end
+      const uint64_t me = ((uint64_t)k << 32) | i;
+      for (uint32_t j = s0; j < s1; j += 2) {
+        const uint32_t j1 = min(j + 1, s1 - 1);
+        const uint64_t o0 = ((uint64_t)placed[j] << 32) | j;
+        const uint64_t o1 = ((uint64_t)placed[j1] << 32) | j1;
+        rank += o0 < me ? 1u : 0u;
+        rank += (j + 1 < s1 && o1 < me) ? 1u : 0u;
+      }
+    } else {
+      for (uint32_t j = s0; j < s1; j++) {
+        const KT o = placed[j];
+        rank += (o < k || (o == k && j < i)) ? 1u : 0u;
+      }
     }
     out[s0 + rank] = from_ord(k, kout);
   }

@@ -537,6 +537,9 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
 constexpr int ROUNDS_LOG2 = 14;   // S = 16384 slots: about one key per slot for 16K-key buckets
 constexpr uint32_t ROUNDS_MAX = 64;     // rounds the LDS bookkeeping has room for
 
+// a 16-bit view of 32-bit LDS words (two slot counters per word)
+typedef uint16_t __attribute__((may_alias)) u16_alias;
+
 template <int CAP>
 struct SlotRoundsLds {
   uint32_t placed[CAP];
@@ -567,20 +570,32 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
   // more than one round needs them apart
   if ((const void*)in == (const void*)out && len > CR) return false;
   if ((len + (CAP - ROUNDS_MAX_FILL) - 1) / (CAP - ROUNDS_MAX_FILL) > ROUNDS_MAX) return false;
-  uint32_t mn = ~0u, mx = 0;
-  if (!(lo_known && hi_known)) {
-    for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
+  // every key of the bucket to fn, eight per thread per step: whole steps
+  // load without bounds tests, the last one clamps its index into the bucket
+  auto each_key = [&](auto&& fn) {
+    uint32_t i0 = 0;
+    for (; i0 + 8 * NTH <= len; i0 += 8 * NTH) {
       uint32_t k[8];
 #pragma unroll
-      for (int u = 0; u < 8; u++) {
-        uint32_t i = i0 + u * NTH + t;
-        k[u] = i < len ? in[i] : 0u;
-      }
+      for (int u = 0; u < 8; u++) k[u] = in[i0 + u * NTH + t];
+#pragma unroll
+      for (int u = 0; u < 8; u++) fn(k[u]);
+    }
+    if (i0 < len) {
+      uint32_t k[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) k[u] = in[min(i0 + u * NTH + t, len - 1)];
 #pragma unroll
       for (int u = 0; u < 8; u++)
-        if (i0 + u * NTH + t < len) { mn = k[u] < mn ? k[u] : mn; mx = k[u] > mx ? k[u] : mx; }
+        if (i0 + u * NTH + t < len) fn(k[u]);
     }
-  }
+  };
+  uint32_t mn = ~0u, mx = 0;
+  if (!(lo_known && hi_known))
+    each_key([&](uint32_t k) {
+      mn = k < mn ? k : mn;
+      mx = k > mx ? k : mx;
+    });
   for (int q = t; q < W; q += NTH) sm.cnt[q] = 0;
   if (!(lo_known && hi_known)) block_minmax<NTH>(mn, mx, (uint32_t*)sm.red);   // (ends with a barrier)
   else __syncthreads();
@@ -593,8 +608,8 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
   const int bw = bit_width<uint32_t>(mx - mn);
   const int sh = bw > LG ? bw - LG : 0;
   auto slot = [&](uint32_t k) { return (k - mn) >> sh; };
-  auto get = [&](uint32_t q) {
-    if constexpr (C16) return (sm.cnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+  auto get = [&](uint32_t q) -> uint32_t {   // (16-bit counter q is half q & 1 of word q >> 1)
+    if constexpr (C16) return ((const u16_alias*)sm.cnt)[q];
     else return sm.cnt[q];
   };
   // old value of slot q's counter, then += 1
@@ -606,22 +621,11 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
       return atomicAdd(&sm.cnt[q], 1u);
     }
   };
-  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
-    uint32_t k[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      uint32_t i = i0 + u * NTH + t;
-      k[u] = i < len ? in[i] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      if (i0 + u * NTH + t < len) {
-        const uint32_t q = slot(k[u]);
-        if constexpr (C16) atomicAdd(&sm.cnt[q >> 1], 1u << (16 * (q & 1)));
-        else atomicAdd(&sm.cnt[q], 1u);
-      }
-    }
-  }
+  each_key([&](uint32_t k) {
+    const uint32_t q = slot(k);
+    if constexpr (C16) atomicAdd(&sm.cnt[q >> 1], 1u << (16 * (q & 1)));
+    else atomicAdd(&sm.cnt[q], 1u);
+  });
   __syncthreads();
   // exclusive scan of the slot counts, and the fullest slot
   {
@@ -687,23 +691,14 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
       const uint32_t q = slot(k);
       if (rounds == 1 || (q >= qa && q < qb)) sm.placed[inc(q) - base] = k;
     };
-    for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
-      uint32_t k[8];
-#pragma unroll
-      for (int u = 0; u < 8; u++) {
-        uint32_t i = i0 + u * NTH + t;
-        k[u] = i < len ? in[i] : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; u++)
-        if (i0 + u * NTH + t < len) place(k[u]);
-    }
+    each_key(place);
     __syncthreads();
     // order each slot (the counter of slot q < qb now holds its end)
     const uint32_t top = (qb < (uint32_t)S ? get(qb - 1) : len) - base;
     slot_rank_write<4, NTH>(sm.placed, top, out + base, kout, [&](uint32_t k, uint32_t& s0, uint32_t& s1) {
       const uint32_t q = slot(k);
-      s0 = (q ? get(q - 1) : 0u) - base;
+      const uint32_t e0 = get(q ? q - 1 : 0u);
+      s0 = (q ? e0 : 0u) - base;
       s1 = get(q) - base;
     });
     __syncthreads();
