@@ -1237,6 +1237,9 @@ __device__ __forceinline__ void slot_rank_write(const typename KeyOf<KW>::T* pla
   }
 }
 
+// a 16-bit view of 32-bit LDS words (two slot counters per word)
+typedef uint16_t __attribute__((may_alias)) u16_alias;
+
 template <int KW> struct SlotCap { static constexpr int C = KW == 4 ? 16128 : 8064; };
 constexpr int SLOT_LOG2 = 13;                   // S = 8192 slots
 constexpr uint32_t SLOT_MAX_FILL = 48;          // crowded-slot limit
@@ -1268,19 +1271,32 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
   constexpr int W = S / 2;
   const int t = threadIdx.x;
   const KT* in = src + beg;
+  // every key of the bucket to fn, eight per thread per step: whole steps
+  // load without bounds tests, the last one clamps its index into the bucket
+  auto each_key = [&](auto&& fn) {
+    uint32_t i0 = 0;
+    for (; i0 + 8 * NTH <= len; i0 += 8 * NTH) {
+      KT k[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) k[u] = to_ord(in[i0 + u * NTH + t], kin);
+#pragma unroll
+      for (int u = 0; u < 8; u++) fn(k[u]);
+    }
+    if (i0 < len) {
+      KT k[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) k[u] = to_ord(in[min(i0 + u * NTH + t, len - 1)], kin);
+#pragma unroll
+      for (int u = 0; u < 8; u++)
+        if (i0 + u * NTH + t < len) fn(k[u]);
+    }
+  };
   KT mn = ~KT(0), mx = 0;
   if (!(lo_known && hi_known))
-  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
-    KT k[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      uint32_t i = i0 + u * NTH + t;
-      k[u] = i < len ? to_ord(in[i], kin) : KT(0);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; u++)
-      if (i0 + u * NTH + t < len) { mn = k[u] < mn ? k[u] : mn; mx = k[u] > mx ? k[u] : mx; }
-  }
+    each_key([&](KT k) {
+      mn = k < mn ? k : mn;
+      mx = k > mx ? k : mx;
+    });
   for (int q = t; q < W; q += NTH) sm.scnt[q] = 0;
   if (!(lo_known && hi_known)) block_minmax<NTH>(mn, mx, (KT*)sm.red);   // (ends with a barrier)
   else __syncthreads();
@@ -1293,21 +1309,10 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
   const int bw = bit_width<KT>((KT)(mx - mn));
   const int sh = bw > SLOT_LOG2 ? bw - SLOT_LOG2 : 0;
   auto slot = [&](KT k) { return (uint32_t)((KT)(k - mn) >> sh); };
-  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
-    KT k[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      uint32_t i = i0 + u * NTH + t;
-      k[u] = i < len ? to_ord(in[i], kin) : KT(0);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      if (i0 + u * NTH + t < len) {
-        uint32_t q = slot(k[u]);
-        atomicAdd(&sm.scnt[q >> 1], 1u << (16 * (q & 1)));
-      }
-    }
-  }
+  each_key([&](KT k) {
+    const uint32_t q = slot(k);
+    atomicAdd(&sm.scnt[q >> 1], 1u << (16 * (q & 1)));
+  });
   __syncthreads();
   // exclusive scan of the slot counts (16-bit halves), and the fullest slot
   {
@@ -1346,24 +1351,15 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
     const uint32_t old = atomicAdd(&sm.scnt[q >> 1], 1u << sft);
     sm.placed[(old >> sft) & 0xFFFFu] = k;
   };
-  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
-    KT k[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      uint32_t i = i0 + u * NTH + t;
-      k[u] = i < len ? to_ord(in[i], kin) : KT(0);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; u++)
-      if (i0 + u * NTH + t < len) place(k[u]);
-  }
+  each_key(place);
   __syncthreads();
   // order each slot: a key's rank = keys of its slot that are smaller, or
   // equal and placed earlier
-  auto slot_end = [&](uint32_t q) { return (sm.scnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu; };
+  auto slot_end = [&](uint32_t q) -> uint32_t { return ((const u16_alias*)sm.scnt)[q]; };
   slot_rank_write<KW, NTH>(sm.placed, len, out + beg, kout, [&](KT k, uint32_t& s0, uint32_t& s1) {
     const uint32_t q = slot(k);
-    s0 = q ? slot_end(q - 1) : 0u;
+    const uint32_t e0 = slot_end(q ? q - 1 : 0u);
+    s0 = q ? e0 : 0u;
     s1 = slot_end(q);
   });
   __syncthreads();

@@ -537,9 +537,6 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
 constexpr int ROUNDS_LOG2 = 14;   // S = 16384 slots: about one key per slot for 16K-key buckets
 constexpr uint32_t ROUNDS_MAX = 64;     // rounds the LDS bookkeeping has room for
 
-// a 16-bit view of 32-bit LDS words (two slot counters per word)
-typedef uint16_t __attribute__((may_alias)) u16_alias;
-
 template <int CAP>
 struct SlotRoundsLds {
   uint32_t placed[CAP];
