@@ -645,7 +645,10 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   const uint32_t pieces = (uint32_t)(cdiv(P.n, WIDE_TB) + WIDE_P1);
   LAUNCH(PK_SPLIT_FINE, k_wide_split_b, dim3(pieces), dim3(NT), 0, st, w);
   LAUNCH_CHECK();
-  LAUNCH(PK_BUCKET_SORT, k_wide_bucket, dim3(w.p), dim3(WIDE_BNT), 0, st, a, w, exp);
+  if (wide_small_rounds(P.n, w.p, P.s))
+    LAUNCH(PK_BUCKET_SORT, (k_wide_bucket<WIDE_SCAP, WIDE_SLG>), dim3(w.p), dim3(WIDE_BNT), 0, st, a, w, exp);
+  else
+    LAUNCH(PK_BUCKET_SORT, (k_wide_bucket<WIDE_BCAP, ROUNDS_LOG2>), dim3(w.p), dim3(WIDE_BNT), 0, st, a, w, exp);
   LAUNCH_CHECK();
   LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<4>), dim3(std::min<uint32_t>(w.p, 512)), dim3(NT), 0, st, a, 0);
   LAUNCH_CHECK();
@@ -678,7 +681,10 @@ int run_sort_first(const Plan& P, char* ws, LevelArgs a, void* out, int exp, hip
   LAUNCH_CHECK();
   a.dst = f.stage;
   a.out = out;
-  LAUNCH(PK_BUCKET_SORT, k_sf_bucket, dim3(f.p), dim3(WIDE_BNT), 0, st, a, f);
+  if (wide_small_rounds(P.n, f.p, P.s))
+    LAUNCH(PK_BUCKET_SORT, (k_sf_bucket<WIDE_SCAP, WIDE_SLG>), dim3(f.p), dim3(WIDE_BNT), 0, st, a, f);
+  else
+    LAUNCH(PK_BUCKET_SORT, (k_sf_bucket<WIDE_BCAP, ROUNDS_LOG2>), dim3(f.p), dim3(WIDE_BNT), 0, st, a, f);
   LAUNCH_CHECK();
   LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<4>), dim3(std::min<uint32_t>(f.p, 512)), dim3(NT), 0, st, a, 0);
   LAUNCH_CHECK();

@@ -137,8 +137,9 @@ __global__ void __launch_bounds__(SF_GNT) k_sf_gather(SfArgs f, uint64_t* exp_co
 // Step 5, second half: one work-group per bucket sorts its gathered keys
 // (they lie between the keys of splitters j and j + 1, both included) with
 // the round-based slot sort; crowded buckets go to the radix sort's list.
+template <int CAP, int LG2>
 __global__ void __launch_bounds__(WIDE_BNT) k_sf_bucket(LevelArgs a, SfArgs f) {
-  __shared__ SlotRoundsLds<WIDE_BCAP> sm;
+  __shared__ SlotRoundsLds<CAP, LG2> sm;
   const uint32_t j = blockIdx.x;
   if (j >= f.p) return;
   const uint2 e = f.bkt[j];
@@ -148,9 +149,9 @@ __global__ void __launch_bounds__(WIDE_BNT) k_sf_bucket(LevelArgs a, SfArgs f) {
   uint32_t* out = (uint32_t*)a.out + e.x;
   bool done = e.y == 0;
   if (!done && e.y <= WIDE_BMAX)
-    done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP>(f.stage + e.x, out, e.y, f.kind, sm, lo_k, lo, hi_k, hi);
+    done = slot_sort_rounds<WIDE_BNT, CAP, true, LG2>(f.stage + e.x, out, e.y, f.kind, sm, lo_k, lo, hi_k, hi);
   else if (!done)
-    done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP, false>(f.stage + e.x, out, e.y, f.kind, sm, lo_k, lo, hi_k, hi);
+    done = slot_sort_rounds<WIDE_BNT, CAP, false, LG2>(f.stage + e.x, out, e.y, f.kind, sm, lo_k, lo, hi_k, hi);
   if (threadIdx.x == 0) {
     if (done) {
       atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)e.y);

@@ -54,6 +54,19 @@ constexpr uint32_t WIDE_TB = 65536;            // nominal keys per piece of the 
 // (one work-group per CU), buckets of up to 65535 keys
 constexpr int WIDE_BNT = 1024;
 constexpr int WIDE_BCAP = 30720;
+// The bucket sorts of the wide split and of sort-first come in two LDS
+// layouts: 30720 keys a round over 2^14 slots (one work-group per CU), or
+// 16000 keys a round over 2^13 slots (two work-groups share a CU, under 80 KB
+// of LDS each).  The second is faster while the buckets take one or two
+// rounds; each further round re-reads the whole bucket, so large or uneven
+// buckets take the first: the second is chosen for a mean bucket of up to
+// 32K keys with an oversampling ratio s >= 16, or up to 16K keys with s >= 8
+// (the largest buckets grow with the mean and shrink with s).
+constexpr int WIDE_SCAP = 16000;
+constexpr int WIDE_SLG = 13;
+inline bool wide_small_rounds(uint64_t n, uint32_t p, uint32_t s) {
+  return (s >= 16 && n <= 32768ull * p) || (s >= 8 && n <= 16384ull * p);
+}
 constexpr uint32_t WIDE_BMAX = 65535;          // largest bucket the round-based slot sort takes
 // expected largest bucket up to which the wide split sorts every bucket in
 // rounds; above it a level below takes the buckets past WIDE_BMAX (on 2^26
@@ -527,20 +540,20 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
 }
 
 // Slot sort of up to 65535 keys in rounds (4-byte ord keys).  As the slot
-// sort of the level kernels: slot(key) = (key - lo) >> sh over S = 16384
+// sort of the level kernels: slot(key) = (key - lo) >> sh over S = 2^LG2
 // slots, count, scan, place, then order each slot's few keys.  A bucket
 // larger than the LDS is handled in rounds: round r places the keys of the
 // slots whose start lies in [r*C', (r+1)*C'), C' = CAP - ROUNDS_MAX_FILL, so
 // a round never holds more than CAP keys.  Each round re-reads the bucket
 // (from L2).  Returns false (having written nothing) when a slot is too
 // crowded or the bucket too large.
-constexpr int ROUNDS_LOG2 = 14;   // S = 16384 slots: about one key per slot for 16K-key buckets
+constexpr int ROUNDS_LOG2 = 14;   // default S = 16384 slots (one work-group per CU: 156 KB of LDS)
 constexpr uint32_t ROUNDS_MAX = 64;     // rounds the LDS bookkeeping has room for
 
-template <int CAP>
+template <int CAP, int LG2 = ROUNDS_LOG2>
 struct SlotRoundsLds {
   uint32_t placed[CAP];
-  uint32_t cnt[(1 << ROUNDS_LOG2) / 2];   // 16-bit slot counts, then starts, then cursors / ends, two per word
+  uint32_t cnt[(1 << LG2) / 2];   // 16-bit slot counts, then starts, then cursors / ends, two per word
   alignas(8) uint64_t red[64];
   uint32_t flag;
   uint32_t rslot[ROUNDS_MAX + 1], rbase[ROUNDS_MAX + 1];   // first slot and first position of each round
@@ -550,14 +563,14 @@ struct SlotRoundsLds {
 // cost that many steps per key)
 constexpr uint32_t ROUNDS_MAX_FILL = 256;
 
-// C16: 16-bit counters over 2^ROUNDS_LOG2 slots (buckets up to 65535 keys);
+// C16: 16-bit counters over 2^LG2 slots (buckets up to 65535 keys);
 // otherwise 32-bit counters over half as many slots in the same LDS
 // (buckets of any size, in more rounds).
-template <int NTH, int CAP, bool C16 = true>
+template <int NTH, int CAP, bool C16 = true, int LG2 = ROUNDS_LOG2>
 __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* out, uint32_t len, int kout,
-                                                 SlotRoundsLds<CAP>& sm, bool lo_known, uint32_t lo, bool hi_known,
+                                                 SlotRoundsLds<CAP, LG2>& sm, bool lo_known, uint32_t lo, bool hi_known,
                                                  uint32_t hi) {
-  constexpr int LG = C16 ? ROUNDS_LOG2 : ROUNDS_LOG2 - 1;
+  constexpr int LG = C16 ? LG2 : LG2 - 1;
   constexpr int S = 1 << LG;
   constexpr int W = C16 ? S / 2 : S;       // counter words
   constexpr uint32_t CR = CAP - ROUNDS_MAX_FILL;
@@ -705,8 +718,9 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
 
 // One fine bucket per work-group: write its tie runs, slot-sort its other
 // keys (or hand them to the leftover list).
+template <int CAP, int LG2>
 __global__ void __launch_bounds__(WIDE_BNT) k_wide_bucket(LevelArgs a, WideArgs w, int export_stages) {
-  __shared__ SlotRoundsLds<WIDE_BCAP> sm;
+  __shared__ SlotRoundsLds<CAP, LG2> sm;
   const uint32_t b = blockIdx.x;
   if (b >= w.p) return;
   const int t = threadIdx.x;
@@ -757,9 +771,9 @@ __global__ void __launch_bounds__(WIDE_BNT) k_wide_bucket(LevelArgs a, WideArgs 
   }
   bool done = sz == 0;
   if (!done && sz <= WIDE_BMAX)
-    done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP>(w.fine + nt0, out + nt0, sz, w.kout, sm, lo_k, lo, hi_k, hi);
+    done = slot_sort_rounds<WIDE_BNT, CAP, true, LG2>(w.fine + nt0, out + nt0, sz, w.kout, sm, lo_k, lo, hi_k, hi);
   else if (!done)
-    done = slot_sort_rounds<WIDE_BNT, WIDE_BCAP, false>(w.fine + nt0, out + nt0, sz, w.kout, sm, lo_k, lo, hi_k, hi);
+    done = slot_sort_rounds<WIDE_BNT, CAP, false, LG2>(w.fine + nt0, out + nt0, sz, w.kout, sm, lo_k, lo, hi_k, hi);
   if (t == 0) {
     if (done) {
       atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)(end - beg));

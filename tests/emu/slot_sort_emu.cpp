@@ -73,12 +73,12 @@ std::vector<Case> make_cases() {
 
 }  // namespace
 
-int main() {
-  std::vector<Case> cs = make_cases();
+// one pass over all cases with the slot sort's LDS laid out for CAP keys a
+// round over 2^LG2 slots; returns the number of wrong buckets
+template <int CAP, int LG2>
+size_t run_cases(const std::vector<Case>& cs, const char* name) {
   constexpr int NTH = WIDE_BNT;
-  static SlotRoundsLds<WIDE_BCAP> sm;
-  g_emu_waves = new EmuWave[NTH / 64];
-  g_emu_block = new std::barrier<>(NTH);
+  static SlotRoundsLds<CAP, LG2> sm;
   std::vector<uint32_t*> ins(cs.size()), outs(cs.size());
   std::vector<int> res(cs.size(), -1);
   for (size_t i = 0; i < cs.size(); i++) {
@@ -93,10 +93,10 @@ int main() {
       for (size_t i = 0; i < cs.size(); i++) {
         const Case& c = cs[i];
         const bool ok = c.len <= WIDE_BMAX
-                            ? slot_sort_rounds<NTH, WIDE_BCAP>(ins[i], outs[i], c.len, 0, sm, c.lo_k, c.lo, c.hi_k,
-                                                               c.hi)
-                            : slot_sort_rounds<NTH, WIDE_BCAP, false>(ins[i], outs[i], c.len, 0, sm, c.lo_k, c.lo,
-                                                                      c.hi_k, c.hi);
+                            ? slot_sort_rounds<NTH, CAP, true, LG2>(ins[i], outs[i], c.len, 0, sm, c.lo_k, c.lo,
+                                                                    c.hi_k, c.hi)
+                            : slot_sort_rounds<NTH, CAP, false, LG2>(ins[i], outs[i], c.len, 0, sm, c.lo_k, c.lo,
+                                                                     c.hi_k, c.hi);
         if (t == 0) res[i] = ok ? 1 : 0;
         __syncthreads();
       }
@@ -107,7 +107,7 @@ int main() {
     const Case& c = cs[i];
     if (c.alias) {   // refused, and the buffer left as it was
       if (res[i] != 0 || !std::equal(c.keys.begin(), c.keys.end(), ins[i])) {
-        printf("aliased case len %u: not refused untouched\n", c.len);
+        printf("%s: aliased case len %u: not refused untouched\n", name, c.len);
         wrong++;
       }
       continue;
@@ -115,7 +115,7 @@ int main() {
     if (res[i] == 0) {
       fell_back++;
       if (!c.may_fall_back) {
-        printf("case %zu len %u handed on unexpectedly\n", i, c.len);
+        printf("%s: case %zu len %u handed on unexpectedly\n", name, i, c.len);
         wrong++;
       }
       continue;
@@ -123,10 +123,24 @@ int main() {
     std::vector<uint32_t> w = c.keys;
     std::sort(w.begin(), w.end());
     if (!std::equal(w.begin(), w.end(), outs[i])) {
-      printf("case %zu len %u: wrong order\n", i, c.len);
+      printf("%s: case %zu len %u: wrong order\n", name, i, c.len);
       wrong++;
     }
   }
-  printf("buckets %zu wrong %zu handed_on %zu\n", cs.size(), wrong, fell_back);
+  for (size_t i = 0; i < cs.size(); i++) {
+    if (outs[i] != ins[i]) delete[] outs[i];
+    delete[] ins[i];
+  }
+  printf("%s: buckets %zu wrong %zu handed_on %zu\n", name, cs.size(), wrong, fell_back);
+  return wrong;
+}
+
+int main() {
+  std::vector<Case> cs = make_cases();
+  g_emu_waves = new EmuWave[WIDE_BNT / 64];
+  g_emu_block = new std::barrier<>(WIDE_BNT);
+  size_t wrong = run_cases<WIDE_BCAP, ROUNDS_LOG2>(cs, "30720 keys, 2^14 slots");
+  wrong += run_cases<WIDE_SCAP, WIDE_SLG>(cs, "16000 keys, 2^13 slots");
+  printf("total wrong %zu \n", wrong);
   return wrong ? 1 : 0;
 }

@@ -1,6 +1,8 @@
 """CPU: the round-based slot sort (the bucket sort of the wide split and of
 handed-on level buckets) run on the host through a HIP emulation, one OS
-thread per GPU thread of a 1024-thread work-group, under AddressSanitizer.
+thread per GPU thread of a 1024-thread work-group, under AddressSanitizer,
+in both LDS layouts the library builds (30720 keys a round over 2^14 slots,
+16000 keys a round over 2^13 slots).
 
 Buckets of 1 to 130,000 keys (one round, two rounds, many rounds with
 32-bit slot counters; full-range, dense, duplicate-heavy and two-valued
@@ -28,4 +30,4 @@ def test_slot_sort_rounds_on_host_emulation(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-3000:])
-    assert " wrong 0 " in r.stdout, r.stdout
+    assert "total wrong 0 " in r.stdout, r.stdout
