@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # on; "traffic" is null for anything else.
 MEASURED_TRAFFIC = {
     ("bucket_sort", 26, 4096, 16, "random", "uniform"): {
-        "src_sha256_16": "67357db10fbca08d",
-        "bytes_per_launch": 548213459,   # k_wide_bucket: FETCH 136,436 KiB x 2 + WRITE 262,494 KiB
+        "src_sha256_16": "c0105971a53b9e20",
+        "bytes_per_launch": 830460762,   # k_wide_bucket<16000, 13>: FETCH 273,953 KiB x 2 + WRITE 263,090 KiB
     },
 }
 
