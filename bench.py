@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # on; "traffic" is null for anything else.
 MEASURED_TRAFFIC = {
     ("bucket_sort", 26, 4096, 16, "random", "uniform"): {
-        "src_sha256_16": "c0105971a53b9e20",
-        "bytes_per_launch": 830460762,   # k_wide_bucket<16000, 13>: FETCH 273,953 KiB x 2 + WRITE 263,090 KiB
+        "src_sha256_16": "ff1a23d1d38e7ccc",
+        "bytes_per_launch": 831738342,   # k_wide_bucket<16000, 13>: FETCH 274,548 KiB x 2 + WRITE 263,148 KiB
     },
 }
 

@@ -1283,9 +1283,10 @@ __device__ __forceinline__ bool slot_sort(const typename KeyOf<KW>::T* src, type
       for (int u = 0; u < 8; u++) fn(k[u]);
     }
     if (i0 < len) {
-      KT k[8];
+      KT k[8] = {};
 #pragma unroll
-      for (int u = 0; u < 8; u++) k[u] = to_ord(in[min(i0 + u * NTH + t, len - 1)], kin);
+      for (int u = 0; u < 8; u++)   // (rows wholly past the end load nothing)
+        if (i0 + u * NTH < len) k[u] = to_ord(in[min(i0 + u * NTH + t, len - 1)], kin);
 #pragma unroll
       for (int u = 0; u < 8; u++)
         if (i0 + u * NTH + t < len) fn(k[u]);

@@ -47,20 +47,33 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
   constexpr int W = S / 2;
   const int t = threadIdx.x;
   if (len > (uint32_t)SlotStableLds<KW, VW>::C) return false;
-  KT mn = ~KT(0), mx = 0;
-  if (!(lo_known && hi_known)) {
-    for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
+  // every key of the bucket to fn, eight per thread per step: whole steps
+  // load without bounds tests, the last one clamps its index into the bucket
+  auto each_key = [&](auto&& fn) {
+    uint32_t i0 = 0;
+    for (; i0 + 8 * NTH <= len; i0 += 8 * NTH) {
       KT k[8];
 #pragma unroll
-      for (int u = 0; u < 8; u++) {
-        uint32_t i = i0 + u * NTH + t;
-        k[u] = i < len ? in[i] : KT(0);
-      }
+      for (int u = 0; u < 8; u++) k[u] = in[i0 + u * NTH + t];
+#pragma unroll
+      for (int u = 0; u < 8; u++) fn(k[u]);
+    }
+    if (i0 < len) {
+      KT k[8] = {};
+#pragma unroll
+      for (int u = 0; u < 8; u++)   // (rows wholly past the end load nothing)
+        if (i0 + u * NTH < len) k[u] = in[min(i0 + u * NTH + t, len - 1)];
 #pragma unroll
       for (int u = 0; u < 8; u++)
-        if (i0 + u * NTH + t < len) { mn = k[u] < mn ? k[u] : mn; mx = k[u] > mx ? k[u] : mx; }
+        if (i0 + u * NTH + t < len) fn(k[u]);
     }
-  }
+  };
+  KT mn = ~KT(0), mx = 0;
+  if (!(lo_known && hi_known))
+    each_key([&](KT k) {
+      mn = k < mn ? k : mn;
+      mx = k > mx ? k : mx;
+    });
   for (int q = t; q < W; q += NTH) sm.scnt[q] = 0;
   if (!(lo_known && hi_known)) block_minmax<NTH>(mn, mx, (KT*)sm.red);   // (ends with a barrier)
   else __syncthreads();
@@ -76,21 +89,10 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
   const int bw = bit_width<KT>((KT)(mx - mn));
   const int sh = bw > SLOT_LOG2 ? bw - SLOT_LOG2 : 0;
   auto slot = [&](KT k) { return (uint32_t)((KT)(k - mn) >> sh); };
-  for (uint32_t i0 = 0; i0 < len; i0 += 8 * NTH) {
-    KT k[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      uint32_t i = i0 + u * NTH + t;
-      k[u] = i < len ? in[i] : KT(0);
-    }
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      if (i0 + u * NTH + t < len) {
-        const uint32_t q = slot(k[u]);
-        atomicAdd(&sm.scnt[q >> 1], 1u << (16 * (q & 1)));
-      }
-    }
-  }
+  each_key([&](KT k) {
+    const uint32_t q = slot(k);
+    atomicAdd(&sm.scnt[q >> 1], 1u << (16 * (q & 1)));
+  });
   __syncthreads();
   // exclusive scan of the slot counts (16-bit halves), and the fullest slot
   {
@@ -126,9 +128,13 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
     VT v[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      const uint32_t i = i0 + u * NTH + t;
-      k[u] = i < len ? in[i] : KT(0);
-      v[u] = i < len ? vin[i] : VT(0);
+      k[u] = KT(0);
+      v[u] = VT(0);
+      if (i0 + u * NTH < len) {   // (rows wholly past the end load nothing)
+        const uint32_t i = min(i0 + u * NTH + t, len - 1);
+        k[u] = in[i];
+        v[u] = vin[i];
+      }
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
@@ -145,16 +151,23 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
   }
   __syncthreads();
   // rank inside the slot by (key, position)
-  auto slot_end = [&](uint32_t q) { return (sm.scnt[q >> 1] >> (16 * (q & 1))) & 0xFFFFu; };
+  auto slot_end = [&](uint32_t q) -> uint32_t { return ((const u16_alias*)sm.scnt)[q]; };
   for (uint32_t j = t; j < len; j += NTH) {
     const KT k = sm.pk[j];
     const uint32_t ip = sm.pi[j];
     const uint32_t q = slot(k);
-    const uint32_t s0 = q ? slot_end(q - 1) : 0u, s1 = slot_end(q);
+    const uint32_t e0 = slot_end(q ? q - 1 : 0u);
+    const uint32_t s0 = q ? e0 : 0u, s1 = slot_end(q);
     uint32_t rank = 0;
-    for (uint32_t o = s0; o < s1; o++) {
-      const KT ko = sm.pk[o];
-      rank += (ko < k || (ko == k && sm.pi[o] < ip)) ? 1u : 0u;
+    if constexpr (KW == 4) {
+      // (key, input position) as one 64-bit number: one compare per key
+      const uint64_t me = ((uint64_t)k << 32) | ip;
+      for (uint32_t o = s0; o < s1; o++) rank += (((uint64_t)sm.pk[o] << 32) | sm.pi[o]) < me ? 1u : 0u;
+    } else {
+      for (uint32_t o = s0; o < s1; o++) {
+        const KT ko = sm.pk[o];
+        rank += (ko < k || (ko == k && sm.pi[o] < ip)) ? 1u : 0u;
+      }
     }
     out[s0 + rank] = from_ord(k, kout);
     vout[s0 + rank] = sm.pv[j];

@@ -592,9 +592,10 @@ __device__ __forceinline__ bool slot_sort_rounds(const uint32_t* in, uint32_t* o
       for (int u = 0; u < 8; u++) fn(k[u]);
     }
     if (i0 < len) {
-      uint32_t k[8];
+      uint32_t k[8] = {};
 #pragma unroll
-      for (int u = 0; u < 8; u++) k[u] = in[min(i0 + u * NTH + t, len - 1)];
+      for (int u = 0; u < 8; u++)   // (rows wholly past the end load nothing)
+        if (i0 + u * NTH < len) k[u] = in[min(i0 + u * NTH + t, len - 1)];
 #pragma unroll
       for (int u = 0; u < 8; u++)
         if (i0 + u * NTH + t < len) fn(k[u]);
