@@ -107,9 +107,9 @@ def test_wide_key_types(dtype):
 
 
 def test_wide_large_buckets_sorted_in_rounds():
-    """2^24 + 777 keys with p = 1024: buckets average 16K keys and reach
-    past the 30K keys one LDS round holds, so the bucket sort takes two
-    rounds for some of them."""
+    """2^24 + 777 keys with p = 1024, s = 16: buckets average 16K keys, so
+    the bucket sort takes its two-work-groups-per-CU layout (16,000 keys a
+    round); the largest pass 30K keys and take two or three rounds."""
     n = (1 << 24) + 777
     keys = workloads.keys_2p26(n, "uniform", workloads.seed_for(5, 2), np.int32)
     kd = torch.from_numpy(keys).cuda()
@@ -169,3 +169,25 @@ def test_wide_in_place_buckets_in_rounds():
     out = api.sort_keys(kd, prm, out=kd)
     assert out.data_ptr() == kd.data_ptr()
     np.testing.assert_array_equal(kd.cpu().numpy(), _sorted_by_oracle(keys))
+
+
+@pytest.mark.parametrize("in_place", [False, True])
+def test_wide_small_layout_many_rounds(in_place):
+    """2^25 + 5 keys with p = 1024, s = 16: a mean bucket of 32K keys with
+    s >= 16 still takes the layout of 16,000 keys a round, and the largest
+    buckets need three rounds or more (each re-reading the bucket while
+    earlier rounds wrote their part of the output).  In place too."""
+    n = (1 << 25) + 5
+    keys = workloads.keys_2p26(n, "uniform", workloads.seed_for(5, 6), np.int32)
+    kd = torch.from_numpy(keys).cuda()
+    prm = api.params(p=1024, s=16, seed=37)
+    note(f"wide small layout 2^25 p=1024 s=16 in_place={in_place}")
+    if in_place:
+        out = api.sort_keys(kd, prm, out=kd)
+        assert out.data_ptr() == kd.data_ptr()
+        got = kd.cpu().numpy()
+    else:
+        out, st, _ = api.stages(kd, prm)
+        assert st["counts"].max() > 2 * (16000 - 256)   # three rounds or more
+        got = out.cpu().numpy()
+    np.testing.assert_array_equal(got, _sorted_by_oracle(keys))
