@@ -520,6 +520,13 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
     sm.g.cur[1][l] = 0;
   }
   __syncthreads();
+  // the subtree's top three levels (nodes 1..7, the same for every key of
+  // the group) from registers: three selects instead of three dependent
+  // LDS reads per key
+  const bool top3 = lg2 >= 3;
+  uint32_t n[8];
+#pragma unroll
+  for (int l = 1; l < 8; l++) n[l] = top3 ? __builtin_amdgcn_readfirstlane(sm.sub[l]) : 0u;
   int x = 0;
   for (uint32_t i0 = r0; i0 < r1; i0 += WIDE_UA * NT, x ^= 1) {
     uint32_t key[WIDE_UA], f[WIDE_UA];
@@ -529,7 +536,19 @@ __global__ void __launch_bounds__(NT) k_wide_split_b(WideArgs w) {
       f[u] = 1;
     }
     if (i0 + WIDE_UA * NT < r1) wide_load(nk, w.stage, i0 + WIDE_UA * NT, r1);
-    for (uint32_t l = 0; l < lg2; l++) {
+    uint32_t l = 0;
+    if (top3) {
+#pragma unroll
+      for (int u = 0; u < WIDE_UA; u++) {
+        const uint32_t k = key[u];
+        const uint32_t a = n[1] < k ? 1u : 0u;
+        const uint32_t b = (a ? n[3] : n[2]) < k ? 1u : 0u;
+        const uint32_t m = a ? (b ? n[7] : n[6]) : (b ? n[5] : n[4]);
+        f[u] = 8 + 4 * a + 2 * b + (m < k ? 1u : 0u);
+      }
+      l = 3;
+    }
+    for (; l < lg2; l++) {
 #pragma unroll
       for (int u = 0; u < WIDE_UA; u++) f[u] = 2 * f[u] + (sm.sub[f[u]] < key[u] ? 1u : 0u);
     }
