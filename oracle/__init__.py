@@ -68,6 +68,8 @@ def _bind(so_path):
     lib.orc_stages.restype = ctypes.c_int
     lib.orc_ord_array.argtypes = [P, U64, ctypes.c_int, P]
     lib.orc_ord_array.restype = None
+    lib.orc_lemma1.argtypes = [U64, ctypes.c_uint32, ctypes.c_uint32, P, P]
+    lib.orc_lemma1.restype = None
     return lib
 
 
@@ -163,16 +165,21 @@ class Oracle:
         return {"sample_ord": so, "sample_tag": st, "spl_ord": po, "spl_tag": pt,
                 "counts": cnt.astype(np.int64), "perm": perm.astype(np.int64)}
 
+    def lemma1_bounds(self, n, p, s):
+        """Bucket-size bounds of Lemma 1 (Section 2.1) for regular
+        oversampling with factor s (the paper's r) and p buckets: with
+        S = s*p samples per block and segment length x = ceil(ceil(n/p)/S),
+        returns (safe, tight, final): safe = (S+p)*x, tight = (S+p-1)*x
+        (the difference bound b_{i+1}-b_i), final = (1+1/s)*n/p + s*p (the
+        lemma's closing expression)."""
+        u = np.zeros(2, np.uint64)
+        d = np.zeros(1, np.float64)
+        self.lib.orc_lemma1(n, p, s, _ptr(u), _ptr(d))
+        return int(u[0]), int(u[1]), float(d[0])
+
 
 def lemma1_bounds(n, p, s):
-    """Bucket-size bounds of Lemma 1 for regular oversampling with factor s
-    (the paper's r) and p buckets: S = s*p samples per block and segment
-    length x = ceil(ceil(n/p)/S).  Returns (safe, tight, final) where
-    safe = (S+p)*x, tight = (S+p-1)*x (the difference bound b_{i+1}-b_i),
-    final = (1+1/s)*n/p + s*p (the lemma's closing expression)."""
-    S = s * p
-    x = -(-(-(-n // p)) // S)
-    return (S + p) * x, (S + p - 1) * x, (1.0 + 1.0 / s) * n / p + s * p
+    return _get().lemma1_bounds(n, p, s)
 
 
 _default = None

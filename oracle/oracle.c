@@ -350,3 +350,24 @@ void orc_ord_array(const void *keys, uint64_t n, int kt, uint64_t *out)
 {
     for (uint64_t i = 0; i < n; i++) out[i] = orc_ord(keys, i, kt);
 }
+
+/* ----------------------------------------------------------- Lemma 1 */
+
+/* Bucket-size bounds of Lemma 1 (Section 2.1) for regular oversampling
+ * with factor r (the API's s) and p buckets.  The proof pads every block to
+ * ceil(n/p) keys and cuts it into S = r*p segments of
+ * x = ceil(ceil(n/p)/S) keys; a splitter has at least i*S*x keys below it
+ * and at least (p*S - i*S - p + 1)*x above it, so two neighbouring
+ * splitters enclose at most S*x + p*x - x keys.
+ *   out_u[0] = (S + p) * x       the bound with the "- x" dropped
+ *   out_u[1] = (S + p - 1) * x   the difference bound b_{i+1} - b_i
+ *   out_d[0] = (1 + 1/r) * n/p + r*p, the lemma's closing expression. */
+void orc_lemma1(uint64_t n, uint32_t p, uint32_t r, uint64_t *out_u, double *out_d)
+{
+    uint64_t S = (uint64_t)r * p;
+    uint64_t blk = (n + p - 1) / p;                                   /* ceil(n/p) */
+    uint64_t x = (ORC_PLANT == 7) ? blk / S : (blk + S - 1) / S;      /* ceil(blk/S) */
+    out_u[0] = (S + p) * x;
+    out_u[1] = (S + p - 1) * x;
+    out_d[0] = (1.0 + 1.0 / (double)r) * (double)n / (double)p + (double)r * (double)p;
+}

@@ -45,3 +45,16 @@ def splitmix64_vectors():
         lines = [l.strip() for l in f if l.strip() and not l.startswith("#")]
     seed = int(lines[0].split()[1])
     return seed, [int(v) for v in lines[1:]]
+
+
+def lemma1_cases():
+    """(n, p, r, safe, tight, final) rows of tests/golden/lemma1.txt."""
+    rows = []
+    with open(os.path.join(GOLDEN, "lemma1.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            t = line.split()
+            rows.append((int(t[0]), int(t[1]), int(t[2]), int(t[3]), int(t[4]), float(t[5])))
+    return rows

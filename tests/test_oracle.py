@@ -86,6 +86,21 @@ def test_float_total_order():
     np.testing.assert_array_equal(vals[sh][oracle.stable_perm(vals[sh])].view(np.uint32), bits)
 
 
+def test_double_total_order():
+    """IEEE 754 totalOrder for binary64: -NaN < -inf < -1 < -0 < +0 < 1 < +inf < +NaN."""
+    bits = np.array([0xFFF8000000000000, 0xFFF0000000000000, 0xBFF0000000000000, 0x8000000000000000,
+                     0x0000000000000000, 0x3FF0000000000000, 0x7FF0000000000000, 0x7FF8000000000000],
+                    dtype=np.uint64)
+    vals = bits.view(np.float64)
+    o = oracle.ord_keys(vals)
+    assert np.all(np.diff(o) > 0)
+    sh = np.random.default_rng(4).permutation(len(vals))
+    np.testing.assert_array_equal(vals[sh][oracle.stable_perm(vals[sh])].view(np.uint64), bits)
+    # -0 and +0 compare equal as floats but sort apart, each keeping input order
+    z = np.array([0.0, -0.0, 0.0, -0.0], dtype=np.float64)
+    np.testing.assert_array_equal(oracle.stable_perm(z), [1, 3, 0, 2])
+
+
 def test_segmented_matches_numpy():
     keys, off = workloads.segmented_keys(50, 11, max_log2=10)
     perm = oracle.segmented_perm(keys, off)
@@ -200,6 +215,17 @@ def test_lemma1_bucket_bound_regular():
         assert mx <= final + 1e-9, (n, p, s, kind, mx, final)
         checked += 1
     assert checked == 300
+
+
+def test_lemma1_bounds_hand_worked():
+    """The bound the Lemma 1 tests check against, pinned to values worked by
+    hand from the lemma's proof (tests/golden/lemma1.txt)."""
+    cases = golden_io.lemma1_cases()
+    assert len(cases) >= 4
+    for n, p, r, safe, tight, final in cases:
+        got = oracle.lemma1_bounds(n, p, r)
+        assert got[0] == safe and got[1] == tight, (n, p, r, got)
+        assert abs(got[2] - final) < 1e-9, (n, p, r, got)
 
 
 def test_p_eff_closed_forms():

@@ -29,6 +29,14 @@ def _stable_ok(orc):
     return True
 
 
+def _lemma1_ok(orc):
+    for n, p, r, safe, tight, final in golden_io.lemma1_cases():
+        got = orc.lemma1_bounds(n, p, r)
+        if got[0] != safe or got[1] != tight or abs(got[2] - final) > 1e-9:
+            return False
+    return True
+
+
 CASES = {
     1: ("merge takes the right run on equal keys", _stable_ok),
     2: ("splitter rank off by one", _golden_ok),
@@ -36,11 +44,12 @@ CASES = {
     4: ("padded segment length rounded down", _golden_ok),
     5: ("tags ignored when keys are equal", _golden_ok),
     6: ("signed keys compared without the sign flip", _stable_ok),
+    7: ("Lemma 1 segment length rounded down", _lemma1_ok),
 }
 
 
 def test_correct_oracle_passes():
-    assert _golden_ok(oracle._get()) and _stable_ok(oracle._get())
+    assert _golden_ok(oracle._get()) and _stable_ok(oracle._get()) and _lemma1_ok(oracle._get())
 
 
 @pytest.mark.parametrize("plant", sorted(CASES))
