@@ -4,21 +4,31 @@
 Default workload: 2^26 int32 keys (uniform, seeded, synthetic), keys only,
 random oversampling with p = 4096 buckets and oversampling s = 16, resident
 in HBM before the timed region.  One step = one full sort: sample, sample
-sort, splitters, classification and counts, scans, the split (for p >= 1024
-in two passes: 64 coarse regions, then the fine buckets) and the bucket
-sorts.  With p < 1024 a top bucket too large for one work-group is split
-once more by the next level before the bucket sorts.
+sort, splitters, classification and counts, the split and the bucket sorts.
 
 Prints ONE JSON line with Gkeys/s, the roofline of the dominant kernel
-(algorithmic bytes / its HIP-event time, against 8 TB/s HBM) and the CPU
-oracle's rate on a bounded sample of the same workload.
+(algorithmic bytes / its HIP-event time, against 8 TB/s HBM), the CPU
+oracle's rate on a bounded sample of the same workload (timed first, on one
+pinned host core, before anything touches the GPU), and -- after the
+headline's timed region -- a "batched" object with the two other forms of
+the metric:
 
-Other workloads (--workload): pairs (2^27 uint64 keys + uint32 payload),
-segmented (20,000 log-uniform segments, one graph-captured call vs one call
-per segment), autograd (64 x 2^18 float32 rows, SortFn forward/backward vs
-per-row calls).
+* segmented: 20,000 segments of log-uniform length in [1, 2^20] (int32),
+  one HIP-graph-captured segmented_sort vs one sample_sort_keys call per
+  segment, both with the library's tuned parameters (prm = NULL);
+* autograd: 64 x 2^18 float32 rows, SortFn forward (values + permutation)
+  and the gradient-scatter backward vs one call per row.
+
+Every output is checked without the oracle: keys non-decreasing and the
+same multiset; a permutation that is a valid permutation, orders the
+values and (tie-free rows) is therefore the unique sorting permutation;
+the backward routes every gradient through it.
+
+Single workloads (--workload): sort, pairs (2^27 uint64 keys + uint32
+payload), segmented, autograd.
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -57,25 +67,51 @@ def parse():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--flags", type=int, default=0, help="extra SS_F_* bits (tuning experiments)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-log2n", type=int, default=24, help="CPU baseline sample size (log2)")
-    ap.add_argument("--profile", action="store_true", help="per-kernel table on stderr")
+    ap.add_argument("--no-batched", action="store_true", help="skip the segmented and autograd forms")
+    ap.add_argument("--cpu-log2n", type=int, default=25, help="CPU baseline sample size (log2)")
+    ap.add_argument("--cpu-runs", type=int, default=3)
     return ap.parse_args()
 
 
-def cpu_baseline(keys, log2n, runs=2):
+# ------------------------------------------------------------ CPU baseline
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(keys, log2n, runs):
     """The oracle (single-threaded C stable merge sort) on a prefix of the
-    same input; Gkeys/s."""
+    same input, pinned to one host core; Gkeys/s as the mean of `runs`
+    runs, the fastest run beside it.  Runs before the GPU is touched."""
     import oracle
     sample = keys[: min(keys.size, 1 << log2n)].copy()
-    ts = []
-    for _ in range(runs):
-        t0 = time.perf_counter()
-        oracle.stable_perm(sample)
-        ts.append(time.perf_counter() - t0)
+    oracle.stable_perm(sample[:1024])                # (builds / loads the oracle outside the timing)
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        ts = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            oracle.stable_perm(sample)
+            ts.append(time.perf_counter() - t0)
+    finally:
+        os.sched_setaffinity(0, old)
     t = sum(ts) / len(ts)
     return {"value": round(sample.size / t / 1e9, 5), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first 2^{int(log2n)} keys of the same input, mean of {runs} runs ({t:.2f} s each)"}
+            "sample": f"first 2^{int(log2n)} keys of the same input, mean of {runs} runs "
+                      f"({t:.2f} s each; fastest {min(ts):.2f} s = {sample.size / min(ts) / 1e9:.5f} Gkeys/s)",
+            "pinned_core": core, "host_cpu": _cpu_model(), "host_cpu_count": os.cpu_count()}
 
+
+# --------------------------------------------------------------- helpers
 
 def fingerprint(a):
     import numpy as np
@@ -141,16 +177,63 @@ def copy_rate(src, dst, reps=5):
     return round(2 * src.numel() * src.element_size() / (ms / 1e3) / 1e9, 1)
 
 
-def bench_sort(args):
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _kernel_table(fn, steps):
+    """Per-kernel HIP-event times of `steps` extra calls (every launch
+    bracketed; outside any timed region)."""
+    from paper_1608_08648_amd import native as N
+    N.profile_enable(True, max_launches=256 * (steps + 1))
+    for _ in range(steps):
+        fn()
+    N.profile_collect()
+    rep = N.profile_report()
+    N.profile_enable(False)
+    return kernel_table(rep, steps)
+
+
+def _segments_sorted(out, inp, off):
+    """Every segment of `out` non-decreasing and a rearrangement of the same
+    segment of `inp` (device tensors; checked on the GPU with torch)."""
+    import torch
+    n = out.numel()
+    seg = torch.repeat_interleave(torch.arange(off.numel() - 1, device=out.device), off[1:] - off[:-1])
+    if seg.numel() != n:
+        return False
+    # non-decreasing inside each segment
+    inc = (out[1:] >= out[:-1]) | (seg[1:] != seg[:-1])
+    if not bool(inc.all()):
+        return False
+    # same multiset per segment: sort (segment, key) pairs of the input with torch and compare
+    ref = torch.sort(seg.to(torch.int64) * (1 << 32) + (inp.to(torch.int64) + (1 << 31)), stable=True).values
+    got = seg.to(torch.int64) * (1 << 32) + (out.to(torch.int64) + (1 << 31))
+    return bool(torch.equal(ref, got))
+
+
+# ------------------------------------------------------- the headline sort
+
+def bench_sort(args, keys):
     import numpy as np
     import torch
 
     from paper_1608_08648_amd import api, native, workloads
 
-    n = 1 << args.log2n
+    n = keys.size
     dev = torch.device("cuda:0")
     seed = workloads.seed_for(1, workloads.DISTRIBUTIONS.index(args.dist))
-    keys = workloads.keys_2p26(n, args.dist, seed, np.int32)
     kd = torch.from_numpy(keys).to(dev)
     out = torch.empty_like(kd)
     prm = api.params(p=args.p, s=args.s, sampling=args.sampling, seed=1234, tile=args.tile, flags=args.flags)
@@ -220,9 +303,197 @@ def bench_sort(args):
         "check": "sorted+multiset" if ok else "FAILED",
         "device_status": status,
     }
-    if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(keys, args.cpu_log2n)
+    del kd, out, ws
+    torch.cuda.empty_cache()
     return res, ok
+
+
+# ------------------------------------------------------------ other forms
+
+def bench_pairs(args):
+    import numpy as np
+    import torch
+
+    from paper_1608_08648_amd import api, native as N, workloads
+
+    n = 1 << 27
+    seed = workloads.seed_for(2)
+    keys, vals = workloads.pairs_dup(n, seed)
+    kd = torch.from_numpy(keys.view(np.int64)).cuda()
+    vd = torch.from_numpy(vals.view(np.int32)).cuda()
+    ko, vo = torch.empty_like(kd), torch.empty_like(vd)
+    # (the stable ballot split takes p <= 256; a larger p uses the generic stable split)
+    prm = api.params(p=args.p if args.p != 4096 else 256, s=args.s, seed=9)
+    ws = api._workspace(api.workspace_size(n, N.SS_U64, N.SS_V_B32, prm), kd.device)
+
+    def step():
+        api.sort_pairs(kd, vd, prm=prm, keys_out=ko, vals_out=vo, ws=ws, key_type="u64")
+
+    ms = _timed(step, args.steps, args.warmup)
+    kernels = _kernel_table(step, max(1, min(args.steps, 5)))
+    ko_h = ko.cpu().numpy().view(np.uint64)
+    vo_h = vo.cpu().numpy().view(np.uint32)
+    # stable: sorted keys, payload (= input index) a permutation that indexes
+    # the keys and increases inside runs of equal keys
+    ok = bool(np.all(ko_h[1:] >= ko_h[:-1]))
+    eq = ko_h[1:] == ko_h[:-1]
+    ok = ok and bool(np.all(vo_h[1:][eq] > vo_h[:-1][eq])) and bool(np.array_equal(keys[vo_h], ko_h))
+    ok = ok and bool(np.bincount(vo_h, minlength=n).max() == 1)
+    gp = n / (ms / 1e3) / 1e9
+    return {"metric": "Gpairs/s, stable sample sort of 2^27 (uint64 key, uint32 payload) pairs",
+            "value": round(gp, 4), "unit": "Gpairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u64+u32", "data": "synthetic",
+            "config": {"workload": "2^27 uint64 keys uniform on [0, 0.7n) with uint32 payload = index, stable",
+                       "p": prm.p, "s": prm.s, "seed": seed},
+            "hbm_frac_56B_per_pair": round(gp * 56 / HBM_PEAK_GBS, 4), "kernels": kernels,
+            "check": "stable order (sorted, payload a permutation increasing in equal-key runs, indexing the keys)"
+            if ok else "FAILED"}, ok
+
+
+def bench_segmented(steps, warmup, per_segment_steps=2):
+    """20,000 log-uniform segments: one graph-captured batched call vs one
+    call per segment, both with the library's tuned parameters (prm = NULL)."""
+    import numpy as np
+    import torch
+
+    from paper_1608_08648_amd import api, native as N, workloads
+
+    count = 20000
+    seed = workloads.seed_for(3)
+    sizes = workloads.segment_sizes(count, seed)
+    off = workloads.offsets_from_sizes(sizes)
+    total, max_len = int(off[-1]), int(sizes.max())
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(seed + 1)
+    kd = torch.randint(-2**31, 2**31, (total,), dtype=torch.int32, device=dev, generator=g)
+    od = torch.from_numpy(off).to(dev)
+    ko = torch.empty_like(kd)
+    wsz = api.segmented_workspace_size(total, count, max_len, N.SS_I32, N.SS_V_NONE, None)
+    ws = api._workspace(wsz, dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        api.segmented_sort(kd, od, max_len=max_len, total=total, keys_out=ko, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        api.segmented_sort(kd, od, max_len=max_len, total=total, keys_out=ko, ws=ws)
+    ms = _timed(graph.replay, steps, warmup)
+    status = api.status(ws)
+    batched = ko.clone()
+    del ws
+    # one call per segment (prm = NULL: the same tuned parameters), workspace
+    # sized for the longest segment
+    ws1 = api._workspace(api.workspace_size(max_len, N.SS_I32, N.SS_V_NONE, None), dev)
+    L = N.lib()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    kin, kout, wp, wn = kd.data_ptr(), ko.data_ptr(), ws1.data_ptr(), ws1.numel()
+    offl = off.tolist()
+
+    def per_segment():
+        for i in range(count):
+            b, e = offl[i], offl[i + 1]
+            if e > b:
+                N.check(L.sample_sort_keys(ctypes.c_void_p(kin + 4 * b), ctypes.c_void_p(kout + 4 * b), e - b,
+                                           N.SS_I32, None, ctypes.c_void_p(wp), wn, stream))
+
+    ko.zero_()
+    ms_seg = _timed(per_segment, per_segment_steps, 1)
+    same = bool(torch.equal(ko, batched))
+    ok = same and _segments_sorted(batched, kd, od) and status == ""
+    gk = total / (ms / 1e3) / 1e9
+    res = {"workload": f"{count} segments, lengths floor(2^(20U)) in [1, 2^20], int32 uniform keys",
+           "segments": count, "total_keys": total, "max_len": max_len, "seed": seed,
+           "params": "tuned (prm = NULL) in both legs",
+           "batched_ms": round(ms, 4), "batched_Gkeys_s": round(gk, 3),
+           "per_segment_ms": round(ms_seg, 3), "per_segment_Gkeys_s": round(total / (ms_seg / 1e3) / 1e9, 3),
+           "speedup": round(ms_seg / ms, 2), "hbm_frac_20B_per_key": round(gk * 20 / HBM_PEAK_GBS, 4),
+           "check": "batched == per-segment; every segment sorted and the same multiset" if ok else "FAILED"}
+    del kd, ko, batched, ws1, od
+    torch.cuda.empty_cache()
+    return res, ok
+
+
+def bench_autograd(steps, warmup):
+    """64 x 2^18 float32 rows: SortFn forward and the gradient-scatter
+    backward vs one call per row."""
+    import torch
+
+    from paper_1608_08648_amd import api, native as N, workloads
+
+    rows, cols = 64, 1 << 18
+    seed = workloads.seed_for(4)
+    x = workloads.tie_free_rows(rows, cols, seed)
+    xd = torch.from_numpy(x).cuda().requires_grad_(True)
+    gy = torch.randn(rows, cols, device="cuda", generator=torch.Generator("cuda").manual_seed(seed))
+
+    def fwd():
+        return api.SortFn.apply(xd)
+
+    vals, perm = fwd()
+    ms_f = _timed(fwd, steps, warmup)
+    gx = api.scatter_grad(gy, perm)
+    ms_b = _timed(lambda: api.scatter_grad(gy, perm, grad_x=gx), steps, warmup)
+
+    ws1 = api._workspace(api.workspace_size(cols, N.SS_F32, N.SS_V_IOTA64, None), xd.device)
+    vrow = torch.empty(rows, cols, dtype=torch.float32, device="cuda")
+    prow = torch.empty(rows, cols, dtype=torch.int64, device="cuda")
+    xdet = xd.detach()
+    L = N.lib()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def fwd_rows():
+        for r in range(rows):
+            N.check(L.sample_sort_pairs(ctypes.c_void_p(xdet[r].data_ptr()), None,
+                                        ctypes.c_void_p(vrow[r].data_ptr()), ctypes.c_void_p(prow[r].data_ptr()),
+                                        cols, N.SS_F32, N.SS_V_IOTA64, None, ctypes.c_void_p(ws1.data_ptr()),
+                                        ws1.numel(), stream))
+
+    gxr = torch.empty_like(gy)
+
+    def bwd_rows():
+        for r in range(rows):
+            api.scatter_grad(gy[r:r + 1], perm[r:r + 1], grad_x=gxr[r:r + 1])
+
+    ms_fr = _timed(fwd_rows, max(1, steps // 2), 1)
+    ms_br = _timed(bwd_rows, max(1, steps // 2), 1)
+    # checks: per-row == batched; perm a permutation of every row that orders
+    # its values (unique on tie-free rows); values == x[perm]; the backward
+    # puts grad_y[r, j] at grad_x[r, perm[r, j]] and nowhere else
+    v = vals.detach()
+    ok = bool(torch.equal(prow, perm)) and bool(torch.equal(vrow, v)) and bool(torch.equal(gxr, gx))
+    ok = ok and bool((v[:, 1:] > v[:, :-1]).all())
+    ok = ok and bool(torch.equal(torch.sort(perm, dim=1).values,
+                                 torch.arange(cols, device="cuda").expand(rows, cols)))
+    ok = ok and bool(torch.equal(torch.gather(xdet, 1, perm), v))
+    ok = ok and bool(torch.equal(torch.gather(gx, 1, perm), gy))
+    n = rows * cols
+    res = {"workload": "64 x 2^18 float32 N(0,1) tie-free rows: SortFn forward, gradient-scatter backward",
+           "rows": rows, "cols": cols, "seed": seed, "params": "tuned (prm = NULL) in both legs",
+           "forward_ms": round(ms_f, 4), "forward_Gelem_s": round(n / (ms_f / 1e3) / 1e9, 3),
+           "backward_ms": round(ms_b, 4), "backward_Gelem_s": round(n / (ms_b / 1e3) / 1e9, 3),
+           "backward_frac_of_hbm_16B": round(n * 16 / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "per_row_forward_ms": round(ms_fr, 4), "per_row_backward_ms": round(ms_br, 4),
+           "speedup_forward": round(ms_fr / ms_f, 2), "speedup_backward": round(ms_br / ms_b, 2),
+           "check": "batched == per-row; perm a permutation ordering each row; backward routes every gradient"
+           if ok else "FAILED"}
+    del xd, gy, vals, perm, gx, gxr, vrow, prow, ws1
+    torch.cuda.empty_cache()
+    return res, ok
+
+
+def _single_line(name, res, args):
+    d = {"metric": {"segmented": "Gkeys/s, batched segmented sample sort (one graph) vs one call per segment",
+                    "autograd": "Gelem/s, differentiable row sort forward of 64 x 2^18 float32"}[name],
+         "value": res["batched_Gkeys_s"] if name == "segmented" else res["forward_Gelem_s"],
+         "unit": "Gkeys/s" if name == "segmented" else "Gelem/s", "n_gpus": 1, "steps": args.steps,
+         "warmup": args.warmup, "ms_per_step": res["batched_ms"] if name == "segmented" else res["forward_ms"],
+         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+         "dtype": "i32" if name == "segmented" else "f32", "data": "synthetic",
+         "config": {"workload": res["workload"]}}
+    d[name] = res
+    return d
 
 
 def main():
@@ -232,10 +503,29 @@ def main():
                                    "measures; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "sort":
-        res, ok = bench_sort(args)
+        import numpy as np
+
+        from paper_1608_08648_amd import workloads
+        seed = workloads.seed_for(1, workloads.DISTRIBUTIONS.index(args.dist))
+        keys = workloads.keys_2p26(1 << args.log2n, args.dist, seed, np.int32)
+        # the CPU baseline first: one pinned core, before anything touches the GPU
+        cpu = None if args.no_cpu else cpu_baseline(keys, args.cpu_log2n, args.cpu_runs)
+        res, ok = bench_sort(args, keys)
+        if cpu is not None:
+            res["cpu_baseline"] = cpu
+        if not args.no_batched:
+            seg, ok1 = bench_segmented(max(2, args.steps // 4), 1)
+            ag, ok2 = bench_autograd(max(4, args.steps // 2), 2)
+            res["batched"] = {"segmented": seg, "autograd": ag}
+            ok = ok and ok1 and ok2
+    elif args.workload == "pairs":
+        res, ok = bench_pairs(args)
+    elif args.workload == "segmented":
+        seg, ok = bench_segmented(args.steps, args.warmup)
+        res = _single_line("segmented", seg, args)
     else:
-        from paper_1608_08648_amd import benchmarks
-        res, ok = getattr(benchmarks, "bench_" + args.workload)(args)
+        ag, ok = bench_autograd(args.steps, args.warmup)
+        res = _single_line("autograd", ag, args)
     print(json.dumps(res), flush=True)
     if not ok:
         sys.exit(1)

@@ -96,6 +96,8 @@ enum { SS_OK = 0, SS_EINVAL = -1, SS_EWORKSPACE = -2, SS_EHIP = -3, SS_EDEVICE =
  *           sampling; the same seed gives the same sample.
  *  flags    SS_F_* bits.
  *  tile     keys per work-group in the split passes (0 = chosen per p).
+ * Every entry point that takes `const ss_params *prm` accepts NULL: the
+ * tuned parameters of the call's size class (ss_get_tuning).
  */
 typedef struct ss_params {
     uint32_t p;
@@ -161,13 +163,48 @@ int ss_segmented_workspace_size(size_t total, size_t num_segments, size_t max_se
  * > 0; `total` must equal offsets[num_segments] and `max_seg_len` bound
  * every segment length (both host values).  Empty segments are allowed.  For
  * the IOTA payload types the payload is the index within the segment.
- * prm may be NULL: then every size class uses tuned defaults; otherwise
- * prm->s, prm->seed and prm->tile apply to every split, and prm->p caps the
- * buckets per segment. */
+ * prm may be NULL: then each segment takes p and s of its size class from
+ * the tuning table (ss_set_tuning); otherwise prm->s, prm->seed and
+ * prm->tile apply to every split, and prm->p caps the buckets per segment.
+ * Segments below one split level are sorted in three classes: up to 64
+ * keys by one wave each, up to 2048 by a work-group with a small LDS
+ * footprint, the rest by a work-group with the full LDS. */
 int segmented_sort(const void *keys_in, const void *vals_in, void *keys_out, void *vals_out,
                    const int64_t *d_offsets, size_t num_segments, size_t total, size_t max_seg_len,
                    int key_type, int val_type, const ss_params *prm, void *ws, size_t ws_bytes,
                    void *stream);
+
+/* Parameters that a call with prm == NULL uses (tuned defaults).  The paper
+ * fixes p for the machine after calibration and ties the sample size to n
+ * (Section 2.1, Section 3); here each size class of the length (class c:
+ * lengths in (2^(c-1), 2^c]) has its own (p, s, tile), per form (single
+ * array or segmented), key width and payload width as sorted (a 64-bit
+ * index payload counts as 4 bytes).  A single sort of n keys uses the
+ * class of n; segmented_sort uses each segment's class for its buckets and
+ * oversampling (tile: the class of max_seg_len).  Sampling is random
+ * (Alg. 2), seed 0x5EED.  The library holds a built-in table measured on an
+ * MI355X; paper_1608_08648_amd.tune measures a new one and installs it. */
+typedef struct ss_tune_entry {
+    uint32_t form;        /* 0 = sample_sort_keys / sample_sort_pairs, 1 = segmented_sort */
+    uint32_t key_bytes;   /* 4 or 8 */
+    uint32_t val_bytes;   /* 0, 4 or 8 */
+    uint32_t size_class;  /* 0..32 */
+    uint32_t p;           /* power of two in [2, SS_P_MAX]; segmented only: 0 = sized from the length */
+    uint32_t s;           /* 1..4096 */
+    uint32_t tile;        /* keys per work-group in the split passes, 0 = chosen per p */
+} ss_tune_entry;
+
+/* Replace the table prm == NULL uses: the built-in table overwritten by
+ * `count` entries (count = 0 restores the built-in table).  Host only; an
+ * invalid entry leaves the table unchanged (SS_EINVAL).  Calls already
+ * enqueued are not affected; calls racing with this one see either table. */
+int ss_set_tuning(const ss_tune_entry *entries, size_t count);
+
+/* The parameters a prm == NULL call of form `form` (0 single, 1 segmented)
+ * on n keys (segmented: a segment of n keys) of these types would use.
+ * Host only.  For the segmented form p = 256 stands for "sized from the
+ * length, at most 256". */
+int ss_get_tuning(int form, int key_type, int val_type, size_t n, ss_params *out);
 
 /* Backward of a row-wise sort y[r, j] = x[r, perm[r, j]]: the gradient goes
  * back through the permutation, grad_x[r, perm[r, j]] = grad_y[r, j].  Each

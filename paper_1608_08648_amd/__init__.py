@@ -7,7 +7,7 @@ tensors to it (``sort_keys``, ``sort_pairs``, ``segmented_sort``,
 """
 import importlib
 
-_SUBMODULES = ("api", "native", "workloads", "build")
+_SUBMODULES = ("api", "native", "workloads", "build", "tune")
 
 
 def __getattr__(name):

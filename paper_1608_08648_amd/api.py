@@ -69,15 +69,32 @@ def _workspace(nbytes, device, ws=None):
     return t[off:off + nbytes]
 
 
+def _pref(prm):
+    """prm by reference, or NULL: the library's tuned parameters (this
+    device's cached tuning table is installed on first use)."""
+    if prm is None:
+        from . import tune
+        tune.ensure_installed()
+        return None
+    return ctypes.byref(prm)
+
+
+def tuned_params(n, key_type, val_type=N.SS_V_NONE, segmented=False):
+    """The parameters the library uses when prm is None (its tuning table)."""
+    out = N.Params()
+    N.check(N.lib().ss_get_tuning(1 if segmented else 0, key_type, val_type, n, ctypes.byref(out)))
+    return out
+
+
 def workspace_size(n, key_type, val_type=N.SS_V_NONE, prm=None):
     out = ctypes.c_size_t()
-    N.check(N.lib().ss_workspace_size(n, key_type, val_type, ctypes.byref(prm or params()), ctypes.byref(out)))
+    N.check(N.lib().ss_workspace_size(n, key_type, val_type, _pref(prm), ctypes.byref(out)))
     return out.value
 
 
 def stage_layout(n, key_type, val_type=N.SS_V_NONE, prm=None):
     info = N.StageInfo()
-    N.check(N.lib().ss_stage_layout(n, key_type, val_type, ctypes.byref(prm or params()), ctypes.byref(info)))
+    N.check(N.lib().ss_stage_layout(n, key_type, val_type, _pref(prm), ctypes.byref(info)))
     return info
 
 
@@ -87,16 +104,30 @@ def _check_dev(*ts):
             raise ValueError("tensors must be contiguous and on the GPU")
 
 
+def _check_buf(name, t, n, width, device):
+    """`t` must hold at least n elements of `width` bytes on `device` (the
+    kernels read or write n elements through its pointer)."""
+    if t is None:
+        return
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the keys on {device}")
+    if t.element_size() != width:
+        raise ValueError(f"{name} has {t.element_size()}-byte elements, {width} needed")
+    if t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, {n} needed")
+
+
 def sort_keys(keys, prm=None, out=None, ws=None, key_type=None, stream=None):
-    """Stable ascending sort of a 1-D tensor of keys."""
-    prm = prm or params()
+    """Stable ascending sort of a 1-D tensor of keys (prm None: the tuned
+    parameters of n's size class)."""
     _check_dev(keys)
     kt = key_type_of(keys, key_type)
     n = keys.numel()
     out = torch.empty_like(keys) if out is None else out
     _check_dev(out)
+    _check_buf("out", out, n, keys.element_size(), keys.device)
     w = _workspace(workspace_size(n, kt, N.SS_V_NONE, prm), keys.device, ws)
-    N.check(N.lib().sample_sort_keys(_ptr(keys), _ptr(out), n, kt, ctypes.byref(prm), _ptr(w), w.numel(),
+    N.check(N.lib().sample_sort_keys(_ptr(keys), _ptr(out), n, kt, _pref(prm), _ptr(w), w.numel(),
                                      _stream(stream)))
     return out
 
@@ -105,8 +136,7 @@ def sort_pairs(keys, vals=None, prm=None, iota=None, keys_out=None, vals_out=Non
                stream=None):
     """Stable sort of (key, payload) pairs by key.  vals: 4- or 8-byte
     payload tensor, or None with iota='int32'/'int64' to get the stable
-    sorting permutation as the payload."""
-    prm = prm or params()
+    sorting permutation as the payload.  prm None: tuned parameters."""
     _check_dev(keys, vals)
     kt = key_type_of(keys, key_type)
     n = keys.numel()
@@ -117,21 +147,25 @@ def sort_pairs(keys, vals=None, prm=None, iota=None, keys_out=None, vals_out=Non
         vdt = torch.int32 if iota == "int32" else torch.int64
         vals_out = torch.empty(n, dtype=vdt, device=keys.device) if vals_out is None else vals_out
     else:
+        if vals.element_size() not in (4, 8):
+            raise ValueError("payloads must have 4- or 8-byte elements")
         vt = {4: N.SS_V_B32, 8: N.SS_V_B64}[vals.element_size()]
+        _check_buf("vals", vals, n, vals.element_size(), keys.device)
         vals_out = torch.empty_like(vals) if vals_out is None else vals_out
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
     _check_dev(keys_out, vals_out)
+    _check_buf("keys_out", keys_out, n, keys.element_size(), keys.device)
+    _check_buf("vals_out", vals_out, n, 4 if vt in (N.SS_V_B32, N.SS_V_IOTA32) else 8, keys.device)
     w = _workspace(workspace_size(n, kt, vt, prm), keys.device, ws)
     N.check(N.lib().sample_sort_pairs(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), n, kt, vt,
-                                      ctypes.byref(prm), _ptr(w), w.numel(), _stream(stream)))
+                                      _pref(prm), _ptr(w), w.numel(), _stream(stream)))
     return keys_out, vals_out
 
 
 def segmented_workspace_size(total, nseg, max_len, key_type, val_type=N.SS_V_NONE, prm=None):
     out = ctypes.c_size_t()
     N.check(N.lib().ss_segmented_workspace_size(total, nseg, max_len, key_type, val_type,
-                                                ctypes.byref(prm) if prm is not None else None,
-                                                ctypes.byref(out)))
+                                                _pref(prm), ctypes.byref(out)))
     return out.value
 
 
@@ -145,24 +179,35 @@ def segmented_sort(keys, offsets, vals=None, iota=None, prm=None, max_len=0, key
     if offsets.dtype != torch.int64:
         raise TypeError("offsets must be int64")
     kt = key_type_of(keys, key_type)
+    if offsets.numel() < 1 or offsets.device != keys.device:
+        raise ValueError("offsets must hold num_segments + 1 entries on the keys' device")
     nseg = offsets.numel() - 1
     if total is None or not max_len:
         o = offsets.cpu()
         total = int(o[-1]) if total is None else total
         max_len = int((o[1:] - o[:-1]).max()) if (nseg > 0 and not max_len) else max_len
+    if total < 0 or total > keys.numel():
+        raise ValueError(f"total = {total}: the keys hold {keys.numel()}")
     if vals is None and iota is not None:
         vt = N.SS_V_IOTA32 if iota == "int32" else N.SS_V_IOTA64
         vdt = torch.int32 if iota == "int32" else torch.int64
         vals_out = torch.empty(keys.numel(), dtype=vdt, device=keys.device) if vals_out is None else vals_out
     elif vals is not None:
+        if vals.element_size() not in (4, 8):
+            raise ValueError("payloads must have 4- or 8-byte elements")
         vt = {4: N.SS_V_B32, 8: N.SS_V_B64}[vals.element_size()]
+        _check_buf("vals", vals, total, vals.element_size(), keys.device)
         vals_out = torch.empty_like(vals) if vals_out is None else vals_out
     else:
         vt = N.SS_V_NONE
     keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    _check_dev(keys_out, vals_out)
+    _check_buf("keys_out", keys_out, total, keys.element_size(), keys.device)
+    if vt != N.SS_V_NONE:
+        _check_buf("vals_out", vals_out, total, 4 if vt in (N.SS_V_B32, N.SS_V_IOTA32) else 8, keys.device)
     w = _workspace(segmented_workspace_size(total, nseg, max_len, kt, vt, prm), keys.device, ws)
     N.check(N.lib().segmented_sort(_ptr(keys), _ptr(vals), _ptr(keys_out), _ptr(vals_out), _ptr(offsets), nseg,
-                                   total, max_len, kt, vt, ctypes.byref(prm) if prm is not None else None,
+                                   total, max_len, kt, vt, _pref(prm),
                                    _ptr(w), w.numel(), _stream(stream)))
     return (keys_out, vals_out) if vt != N.SS_V_NONE else keys_out
 
@@ -173,6 +218,10 @@ def scatter_grad(grad_y, perm, grad_x=None, stream=None):
     if perm.dtype != torch.int64 or perm.shape != grad_y.shape or grad_y.dim() != 2:
         raise ValueError("perm must be int64 with grad_y's 2-D shape")
     grad_x = torch.empty_like(grad_y) if grad_x is None else grad_x
+    _check_dev(grad_x)
+    if grad_x.shape != grad_y.shape or grad_x.element_size() != grad_y.element_size() \
+            or grad_x.device != grad_y.device or perm.device != grad_y.device:
+        raise ValueError("grad_x must match grad_y's shape, element size and device")
     N.check(N.lib().ss_scatter_grad(_ptr(grad_y), _ptr(perm), _ptr(grad_x), grad_y.shape[0], grad_y.shape[1],
                                     grad_y.element_size(), _stream(stream)))
     return grad_x
@@ -202,6 +251,8 @@ def level_stats(ws, stream=None):
 def stages(keys, prm, key_type=None):
     """Run sort_keys with the stage export on and return (sorted keys, dict of
     the top-level sorted sample, splitters and bucket counts, StageInfo)."""
+    if prm is None:
+        prm = tuned_params(keys.numel(), key_type_of(keys, key_type))
     prm = N.Params.from_buffer_copy(prm)
     prm.flags |= N.SS_F_EXPORT_STAGES
     kt = key_type_of(keys, key_type)

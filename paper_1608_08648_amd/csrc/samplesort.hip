@@ -11,11 +11,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 using namespace ss;
@@ -54,31 +56,48 @@ const char* const PROF_NAMES[PK_COUNT] = {
     "bucket_sort", "bucket_leftover", "small_sort", "regular_blocks", "scatter_grad", "split_coarse",
     "split_fine", "sf_search", "sf_gather", "widen"};
 
+// The profiling state is shared by every host thread: `on` is read without
+// the lock on each launch (so sorts cost nothing extra while profiling is
+// off); everything else is touched under `mu`.
 struct Prof {
-  bool on = false;
-  int force = -1;                   // kind every launch counts as (a nested sort's launches), or -1
+  std::atomic<bool> on{false};
+  std::mutex mu;
   uint32_t mask = ~0u;              // kinds that get events
   int cap = 0, used = 0;
   std::vector<hipEvent_t> ev;       // 2 per launch
   std::vector<int> kind;
   double total[PK_COUNT] = {};
   uint64_t count[PK_COUNT] = {};
+  void reset() {
+    mask = ~0u;
+    cap = used = 0;
+    ev.clear();
+    kind.clear();
+    for (int i = 0; i < PK_COUNT; i++) total[i] = 0.0, count[i] = 0;
+  }
 };
 Prof g_prof;
+// kind every launch of this thread counts as (a nested sort's launches), or -1
+thread_local int g_prof_force = -1;
 
 // bracket one launch with events (no-op unless profiling is on)
 struct ProfScope {
   int slot = -1;
   hipStream_t st;
   ProfScope(int k, hipStream_t s) : st(s) {
-    if (g_prof.force >= 0) k = g_prof.force;
-    if (!g_prof.on || !((g_prof.mask >> k) & 1u) || g_prof.used >= g_prof.cap) return;
+    if (!g_prof.on.load(std::memory_order_acquire)) return;
+    if (g_prof_force >= 0) k = g_prof_force;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (!g_prof.on.load(std::memory_order_relaxed) || !((g_prof.mask >> k) & 1u) || g_prof.used >= g_prof.cap)
+      return;
     slot = g_prof.used++;
     g_prof.kind[slot] = k;
     hipEventRecord(g_prof.ev[2 * slot], st);
   }
   ~ProfScope() {
-    if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot + 1], st);
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (slot < (int)g_prof.kind.size()) hipEventRecord(g_prof.ev[2 * slot + 1], st);
   }
 };
 #define LAUNCH(kind, ...)                 \
@@ -166,6 +185,62 @@ uint32_t default_tile(uint32_t p) {
   return (uint32_t)(cdiv(t, TILE_UNIT) * TILE_UNIT);
 }
 
+// ------------------------------------------------------- tuned parameters
+//
+// What a call with prm == NULL uses, per size class: class c holds lengths
+// in (2^(c-1), 2^c] (c = ceil(lg n)), per form (single array, segmented),
+// key width (4, 8) and payload width as sorted (0, 4, 8; a 64-bit index is
+// sorted as a 4-byte one).  The paper chooses p for the machine after
+// calibration (Section 2.1, Section 3); here the table holds what a tuning
+// run on an MI355X measured fastest, and ss_set_tuning replaces it with a
+// newer run's.  In the segmented table p = 0 means "sized from the
+// segment's length" (buckets of about half what one work-group sorts).
+struct TuneTab {
+  uint16_t p[33], s[33];
+  uint32_t tile[33];
+};
+TuneTab g_tune[2][2][3];   // [form][key width 4, 8][payload 0, 4, 8]
+bool g_tune_ready = false;
+std::mutex g_tune_mu;
+
+int size_class(uint64_t n) {
+  int c = 0;
+  while (c < 32 && (1ull << c) < n) c++;
+  return c;
+}
+
+// Built-in table.  Single arrays, keys only: buckets of ~16K 4-byte keys
+// (p up to 4096), ~8K 8-byte keys (p up to 1024); with a payload p <= 256
+// (the stable ballot split); s = 16.  Segmented: p from the length, s = 8.
+void tune_builtin(TuneTab (&t)[2][2][3]) {
+  for (int kw = 0; kw < 2; kw++)
+    for (int vw = 0; vw < 3; vw++)
+      for (int c = 0; c <= 32; c++) {
+        uint32_t p;
+        if (vw == 0 && kw == 0) p = c > 15 ? (1u << std::min(c - 14, 12)) : 2u;
+        else if (vw == 0) p = c > 14 ? (1u << std::min(c - 13, 10)) : 2u;
+        else p = c > 14 ? (1u << std::min(c - 13, 8)) : 2u;
+        t[0][kw][vw].p[c] = (uint16_t)std::max<uint32_t>(p, 2);
+        t[0][kw][vw].s[c] = 16;
+        t[0][kw][vw].tile[c] = 0;
+        t[1][kw][vw].p[c] = 0;
+        t[1][kw][vw].s[c] = 8;
+        t[1][kw][vw].tile[c] = 0;
+      }
+}
+
+const TuneTab& tune_for(int form, int KW, int VW) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune_ready) {
+    tune_builtin(g_tune);
+    g_tune_ready = true;
+  }
+  return g_tune[form][KW == 8 ? 1 : 0][VW == 0 ? 0 : (VW == 4 ? 1 : 2)];
+}
+
+// payload width as sorted (a 64-bit index travels as a 32-bit one)
+int sorted_vw(const Types& ty) { return (ty.iota && ty.VW == 8) ? 4 : ty.VW; }
+
 struct LevelPlan {
   uint32_t tile = 0, seg_cap = 0, pmax = 256, p_cap = 256, target = 0, s = 1;
   uint64_t samp_cap = 0, tiles_cap = 0, hist_cap = 0, bkt_cap = 0;
@@ -183,19 +258,46 @@ struct LevelsPlan {
 // Shapes of the split levels.  Level 0 either has one segment with given p0
 // and sample size m0 (single sort) or up to seg_cap0 segments sized on the
 // device (p0 == 0).  N = total elements, maxlen0 = longest top segment.
+// Segments sized on the device take p and s from the tuning table `tab`
+// (when given): the level's target bucket size is then the smallest that a
+// tuned class asks for, so that the table's p never exceeds what the
+// target rule would give (the capacities below are sized by that rule),
+// and the expected largest bucket follows the table class by class.
+uint32_t tab_target(const TuneTab& tab, uint32_t C, uint64_t maxlen, uint32_t target) {
+  for (int c = size_class((uint64_t)C + 1); c <= size_class(maxlen); c++) {
+    if (!tab.p[c]) continue;
+    const uint64_t b = (c ? (1ull << (c - 1)) : 1ull) / tab.p[c];
+    target = (uint32_t)std::min<uint64_t>(target, std::max<uint64_t>(b, 256));
+  }
+  return target;
+}
+
 void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint64_t maxlen0, uint32_t p0,
                  uint64_t m0, uint64_t est_max0, uint32_t s, uint32_t p_cap, uint32_t tile_req, bool recurse,
-                 LevelsPlan* P, uint32_t cpush0 = 0) {
+                 LevelsPlan* P, uint32_t cpush0 = 0, const TuneTab* tab = nullptr) {
   const uint32_t C = small_cap(ty.KW, ty.VW);
   // buckets larger than this go one level down when there is a level below
   // (keys only: beyond the slot sort's capacity)
   const uint32_t Cpush = ty.VW == 0 ? slot_cap(ty.KW) : C;
   const uint32_t Cs = sample_cap(ty.KW);
-  const double f = spread(s);
+  double f = spread(s);
   // automatically sized buckets aim at about half of what the bucket sort
   // takes in one work-group (the slot sort for keys only)
-  const uint32_t target = ty.VW == 0 ? (uint32_t)(0.53 * slot_cap(ty.KW))
-                                     : (uint32_t)std::max(1024.0, (double)C / (1.2 * f));
+  uint32_t target = ty.VW == 0 ? (uint32_t)(0.53 * slot_cap(ty.KW))
+                               : (uint32_t)std::max(1024.0, (double)C / (1.2 * f));
+  if (tab) {
+    target = tab_target(*tab, C, maxlen0, target);
+    for (int c = size_class((uint64_t)C + 1); c <= size_class(maxlen0); c++)
+      f = std::max(f, spread(tab->s[c] ? tab->s[c] : s));
+  }
+  // expected largest bucket after splitting segments of up to `len` keys
+  auto after = [&](uint64_t len) -> uint64_t {
+    double b = std::max<double>(target, (double)len / p_cap);
+    if (tab)
+      for (int c = size_class((uint64_t)C + 1); c <= size_class(len); c++)
+        if (tab->p[c]) b = std::max(b, std::min<double>((double)len, (double)(1ull << c)) / std::max<uint32_t>(tab->p[c], 2));
+    return (uint64_t)(b * f);
+  };
   P->nlev = 0;
   uint64_t est = 0;
   for (int l = 0; l < MAX_LEVELS; l++) {
@@ -224,7 +326,7 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
       lv.hist_cap = (uint64_t)p_cap * lv.tiles_cap;
       lv.samp_cap = std::min<uint64_t>((uint64_t)Cs * lv.seg_cap, (uint64_t)s * lv.bkt_cap);
       uint64_t len = (l == 0) ? maxlen0 : est;
-      est = (uint64_t)(std::max<double>(target, (double)len / p_cap) * f);
+      est = after(len);
     }
     lv.o_segs = L.take(sizeof(SegDesc) * lv.seg_cap);
     lv.o_sord = L.take((size_t)ty.KW * std::max<uint64_t>(lv.samp_cap, 1));
@@ -268,7 +370,7 @@ struct Plan {
   size_t o_ctl = 0, o_tmp = 0, o_vtmp = 0;
   size_t o_exp_so = 0, o_exp_st = 0, o_exp_po = 0, o_exp_pt = 0, o_exp_cnt = 0;
   bool exp = false;
-  size_t o_small = 0;      // segmented: small-segment list
+  size_t o_small = 0, o_tiny = 0, o_mid = 0;   // segmented: lists of segments below one level
   // regular sampling: sorted blocks and the nested segmented plan
   size_t o_regk = 0, o_regi = 0, o_regoff = 0, o_nested = 0;
   Plan* nested = nullptr;
@@ -284,6 +386,9 @@ struct Plan {
   // a large sample of 4-byte keys: packed records and the nested sort that orders them
   Plan* nested_s = nullptr;
   size_t o_spack = 0, o_nested_s = 0;
+  // segmented without user parameters: the tuning table's p and s per size class
+  bool use_tab = false;
+  TuneTab tab{};
   // a 64-bit index payload sorted as a 32-bit one, then widened
   bool widen = false;
   size_t o_widen = 0;
@@ -294,13 +399,18 @@ struct Plan {
   }
 };
 
-int check_params(const ss_params* prm, ss_params* out) {
+int check_params(const ss_params* prm, ss_params* out, const Types& ty, uint64_t n, int form = 0) {
   ss_params d{};
-  d.p = 1024;
-  d.s = 8;
   d.sampling = SS_RANDOM;
   d.stable = 1;
   d.seed = 0x5EEDull;
+  {
+    const TuneTab& t = tune_for(form, ty.KW, sorted_vw(ty));
+    const int c = size_class(n);
+    d.p = t.p[c] ? t.p[c] : 256;    // (segmented p = 0: sized on the device, at most 256)
+    d.s = t.s[c];
+    d.tile = t.tile[c];
+  }
   if (prm) d = *prm;
   if (d.p < 2 || d.p > SS_P_MAX || (d.p & (d.p - 1))) return fail(SS_EINVAL, "p = %u: need a power of two in [2, %u]", d.p, SS_P_MAX);
   if (d.s < 1 || d.s > 4096) return fail(SS_EINVAL, "s = %u: need 1 <= s <= 4096", d.s);
@@ -449,14 +559,29 @@ int plan_segmented_t(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, co
   Layout L;
   P->o_ctl = L.take(sizeof(Ctl));
   P->o_small = L.take(sizeof(SmallEnt) * std::max<uint64_t>(nseg, 1));
+  P->o_tiny = L.take(sizeof(SmallEnt) * std::max<uint64_t>(nseg, 1));
+  P->o_mid = L.take(sizeof(SmallEnt) * std::max<uint64_t>(nseg, 1));
   P->s = prm.s;
-  const uint32_t p_cap = user_params ? std::min<uint32_t>(prm.p, 4096) : 256;
+  // user parameters: prm->p caps every segment's buckets and prm->s
+  // applies to all; otherwise p and s come from the tuning table per size
+  // class of each segment
+  uint32_t p_cap = std::min<uint32_t>(prm.p, 4096);
+  const TuneTab* tab = nullptr;
+  if (!user_params) {
+    tab = &tune_for(1, ty.KW, ty.VW);
+    p_cap = 2;
+    for (int c = size_class((uint64_t)C + 1); c <= size_class(maxlen); c++)
+      p_cap = std::max<uint32_t>(p_cap, tab->p[c] ? tab->p[c] : 256u);
+    p_cap = std::min<uint32_t>(p_cap, 4096);
+    P->tab = *tab;
+    P->use_tab = true;
+  }
   if (maxlen > C) {
     P->o_tmp = L.take((size_t)ty.KW * total);
     P->o_vtmp = ty.VW ? L.take((size_t)ty.VW * total) : 0;
     uint64_t seg_cap0 = std::min<uint64_t>(nseg, total / (C + 1) + 1);
     const bool recurse = !(prm.flags & SS_F_NO_RECURSION);
-    plan_levels(L, ty, total, seg_cap0, maxlen, 0, 0, 0, prm.s, p_cap, prm.tile, recurse, &P->lp);
+    plan_levels(L, ty, total, seg_cap0, maxlen, 0, 0, 0, prm.s, p_cap, prm.tile, recurse, &P->lp, 0, tab);
   }
   P->bytes = L.cur;
   return SS_OK;
@@ -572,6 +697,12 @@ LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void*
   a.s = lv.s;
   a.p_cap = lv.p_cap;
   a.target = lv.target;
+  a.use_tab = P.use_tab ? 1u : 0u;
+  if (P.use_tab)
+    for (int c = 0; c <= 32; c++) {
+      a.tab_p[c] = P.tab.p[c];
+      a.tab_s[c] = P.tab.s[c];
+    }
   a.kin = (l == 0) ? P.ty.kind : 0;   // the top level writes unsigned images for every deeper pass
   a.kout = P.ty.kind;
   a.iota = (l == 0 && P.ty.iota) ? 1 : 0;
@@ -717,9 +848,9 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
         LAUNCH(PK_SAMPLE_SORT, k_pack_sample, dim3(grid_of(P.m, 256, 4096)), dim3(256), 0, st,
                (const uint32_t*)a.s_ord, (const uint32_t*)a.s_tag, pk, (uint64_t)P.m);
         LAUNCH_CHECK();
-        g_prof.force = PK_SAMPLE_SORT;
+        g_prof_force = PK_SAMPLE_SORT;
         const int rc = run_single_any(*P.nested_s, ws + P.o_nested_s, pk, nullptr, pk, nullptr, st);
-        g_prof.force = -1;
+        g_prof_force = -1;
         if (rc) return rc;
         LAUNCH(PK_SAMPLE_SORT, k_unpack_sample, dim3(grid_of(P.m, 256, 4096)), dim3(256), 0, st,
                (const uint64_t*)pk, (uint32_t*)a.s_ord, a.s_tag, (uint64_t)P.m);
@@ -825,11 +956,26 @@ int run_segmented(const Plan& P, char* ws, const void* in, const void* vin, void
   SegDesc* top = P.lp.nlev ? (SegDesc*)(ws + P.lp.lv[0].o_segs) : nullptr;
   uint32_t top_cap = P.lp.nlev ? P.lp.lv[0].seg_cap : 0;
   LAUNCH(PK_INIT, k_seg_init, dim3(grid_of(P.nseg, 256, 1024)), dim3(256), 0, st, g, off, (uint32_t)P.nseg,
-                     P.lp.nlev ? C : 0xFFFFFFFFu, top, top_cap, (SmallEnt*)(ws + P.o_small), P.prm.seed);
+                     P.lp.nlev ? C : 0xFFFFFFFFu, top, top_cap, (SmallEnt*)(ws + P.o_small),
+                     (SmallEnt*)(ws + P.o_tiny), (SmallEnt*)(ws + P.o_mid), P.prm.seed, (uint64_t)P.n,
+                     (uint64_t)P.maxlen);
   LAUNCH_CHECK();
-  LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)), dim3(NT), 0, st, g,
-                     (const SmallEnt*)(ws + P.o_small), in, vin, out, vout, P.ty.kind, P.ty.iota ? 1 : 0);
+  // the three classes below one split level, each launch sized for every
+  // segment falling into it (the lists are filled on the device)
+  const int iota = P.ty.iota ? 1 : 0;
+  LAUNCH(PK_SMALL_SORT, (k_sort_tiny_list<KW, VW>), dim3(grid_of(P.nseg, NT / WAVE, 8192)), dim3(NT), 0, st, g,
+         (const SmallEnt*)(ws + P.o_tiny), in, vin, out, vout, P.ty.kind, iota);
   LAUNCH_CHECK();
+  if (P.maxlen > WAVE) {
+    LAUNCH(PK_SMALL_SORT, (k_sort_mid_list<KW, VW>), dim3(grid_of(P.nseg, 1, 8192)), dim3(NT), 0, st, g,
+           (const SmallEnt*)(ws + P.o_mid), in, vin, out, vout, P.ty.kind, iota);
+    LAUNCH_CHECK();
+  }
+  if (P.maxlen > MID_CAP) {
+    LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)), dim3(NT), 0,
+           st, g, (const SmallEnt*)(ws + P.o_small), in, vin, out, vout, P.ty.kind, iota);
+    LAUNCH_CHECK();
+  }
   return run_levels<KW, VW>(P, ws, in, vin, out, vout, st);
 }
 
@@ -931,7 +1077,7 @@ int sort_common(const void* keys_in, const void* vals_in, void* keys_out, void* 
   int rc = parse_types(key_type, val_type, &ty);
   if (rc) return rc;
   ss_params p;
-  rc = check_params(prm, &p);
+  rc = check_params(prm, &p, ty, n);
   if (rc) return rc;
   if (n == 0) return SS_OK;
   if (!keys_in || !keys_out) return fail(SS_EINVAL, "keys_in and keys_out must be device pointers");
@@ -966,7 +1112,7 @@ int ss_workspace_size(size_t n, int key_type, int val_type, const ss_params* prm
   int rc = parse_types(key_type, val_type, &ty);
   if (rc) return rc;
   ss_params p;
-  rc = check_params(prm, &p);
+  rc = check_params(prm, &p, ty, n);
   if (rc) return rc;
   Plan P;
   rc = plan_single(&P, n, ty, p);
@@ -982,7 +1128,7 @@ int ss_stage_layout(size_t n, int key_type, int val_type, const ss_params* prm, 
   int rc = parse_types(key_type, val_type, &ty);
   if (rc) return rc;
   ss_params p;
-  rc = check_params(prm, &p);
+  rc = check_params(prm, &p, ty, n);
   if (rc) return rc;
   Plan P;
   rc = plan_single(&P, n, ty, p);
@@ -1025,7 +1171,7 @@ int ss_segmented_workspace_size(size_t total, size_t num_segments, size_t max_se
   int rc = parse_types(key_type, val_type, &ty);
   if (rc) return rc;
   ss_params p;
-  rc = check_params(prm, &p);
+  rc = check_params(prm, &p, ty, max_seg_len ? max_seg_len : total, 1);
   if (rc) return rc;
   Plan P;
   rc = plan_segmented(&P, total, num_segments, max_seg_len, ty, p, prm != nullptr);
@@ -1042,7 +1188,7 @@ int segmented_sort(const void* keys_in, const void* vals_in, void* keys_out, voi
   int rc = parse_types(key_type, val_type, &ty);
   if (rc) return rc;
   ss_params p;
-  rc = check_params(prm, &p);
+  rc = check_params(prm, &p, ty, max_seg_len ? max_seg_len : total, 1);
   if (rc) return rc;
   if (num_segments == 0 || total == 0) return SS_OK;
   if (!keys_in || !keys_out || !d_offsets) return fail(SS_EINVAL, "keys and offsets must be device pointers");
@@ -1092,28 +1238,70 @@ int ss_scatter_grad(const void* grad_y, const int64_t* perm, void* grad_x, size_
   return SS_OK;
 }
 
+int ss_set_tuning(const ss_tune_entry* entries, size_t count) {
+  g_err[0] = 0;
+  if (count && !entries) return fail(SS_EINVAL, "entries is NULL");
+  TuneTab t[2][2][3];
+  tune_builtin(t);
+  for (size_t i = 0; i < count; i++) {
+    const ss_tune_entry& e = entries[i];
+    if (e.form > 1 || (e.key_bytes != 4 && e.key_bytes != 8) ||
+        (e.val_bytes != 0 && e.val_bytes != 4 && e.val_bytes != 8) || e.size_class > 32)
+      return fail(SS_EINVAL, "tuning entry %zu: form %u, key_bytes %u, val_bytes %u, size_class %u", i, e.form,
+                  e.key_bytes, e.val_bytes, e.size_class);
+    const bool auto_p = e.form == 1 && e.p == 0;
+    if ((!auto_p && (e.p < 2 || e.p > SS_P_MAX || (e.p & (e.p - 1)))) || e.s < 1 || e.s > 4096 ||
+        e.tile > (1u << 24))
+      return fail(SS_EINVAL, "tuning entry %zu: p = %u, s = %u, tile = %u", i, e.p, e.s, e.tile);
+    TuneTab& tt = t[e.form][e.key_bytes == 8][e.val_bytes == 0 ? 0 : (e.val_bytes == 4 ? 1 : 2)];
+    tt.p[e.size_class] = (uint16_t)e.p;
+    tt.s[e.size_class] = (uint16_t)e.s;
+    tt.tile[e.size_class] = e.tile;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int f = 0; f < 2; f++)
+    for (int a = 0; a < 2; a++)
+      for (int b = 0; b < 3; b++) g_tune[f][a][b] = t[f][a][b];
+  g_tune_ready = true;
+  return SS_OK;
+}
+
+int ss_get_tuning(int form, int key_type, int val_type, size_t n, ss_params* out) {
+  g_err[0] = 0;
+  if (!out) return fail(SS_EINVAL, "out is NULL");
+  if (form != 0 && form != 1) return fail(SS_EINVAL, "form %d: 0 (single array) or 1 (segmented)", form);
+  Types ty;
+  int rc = parse_types(key_type, val_type, &ty);
+  if (rc) return rc;
+  return check_params(nullptr, out, ty, n, form);
+}
+
 int ss_profile_enable(int on, int max_launches) {
   g_err[0] = 0;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on.store(false, std::memory_order_release);
   for (hipEvent_t e : g_prof.ev) hipEventDestroy(e);
-  g_prof = Prof();
+  g_prof.reset();
   if (!on) return SS_OK;
   if (max_launches < 1 || max_launches > (1 << 20)) return fail(SS_EINVAL, "max_launches out of range");
   g_prof.ev.resize(2 * (size_t)max_launches);
   g_prof.kind.resize(max_launches);
   for (auto& e : g_prof.ev) HIP_TRY(hipEventCreate(&e));
   g_prof.cap = max_launches;
-  g_prof.on = true;
+  g_prof.on.store(true, std::memory_order_release);
   return SS_OK;
 }
 
 int ss_profile_kinds(unsigned kind_mask) {
   g_err[0] = 0;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.mask = kind_mask;
   return SS_OK;
 }
 
 int ss_profile_collect(void) {
   g_err[0] = 0;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   for (int i = 0; i < g_prof.used; i++) {
     HIP_TRY(hipEventSynchronize(g_prof.ev[2 * i + 1]));
     float ms = 0.f;
@@ -1127,6 +1315,7 @@ int ss_profile_collect(void) {
 
 int ss_profile_report(int kind, const char** name, double* total_ms, uint64_t* launches) {
   if (kind < 0 || kind >= PK_COUNT) return SS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   if (name) *name = PROF_NAMES[kind];
   if (total_ms) *total_ms = g_prof.total[kind];
   if (launches) *launches = g_prof.count[kind];
@@ -1156,7 +1345,9 @@ int ss_status(const void* ws, void* stream) {
   HIP_TRY(hipStreamSynchronize(as_stream(stream)));
   uint32_t st = 0;
   HIP_TRY(hipMemcpy(&st, ws, sizeof st, hipMemcpyDeviceToHost));
-  if (st & ST_BAD_OFFSETS) return fail(SS_EDEVICE, "segment offsets decrease (status 0x%x)", st);
+  if (st & ST_BAD_OFFSETS)
+    return fail(SS_EDEVICE, "segment offsets decrease, leave [0, total) or exceed max_seg_len; those segments "
+                            "were skipped (status 0x%x)", st);
   if (st) snprintf(g_err, sizeof g_err, "note: status 0x%x%s%s", st,
                    (st & ST_FALLBACK) ? " (a bucket was sorted by the one-work-group fallback)" : "",
                    (st & ST_LIST_FULL) ? " (a split-level list was full)" : "");

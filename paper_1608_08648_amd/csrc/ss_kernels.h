@@ -97,8 +97,9 @@ struct SmallEnt { uint64_t beg; uint32_t len; uint32_t pad; };
 
 struct Ctl {              // device control block at the start of the workspace
   uint32_t status;        // SS_ST_* bits
-  uint32_t nsmall;        // entries in the small-segment list
-  uint32_t pad[2];
+  uint32_t nsmall;        // entries in the small-segment list (up to one work-group's capacity)
+  uint32_t ntiny;         // entries in the tiny-segment list (up to 64 keys: one wave each)
+  uint32_t nmid;          // entries in the mid-segment list (up to MID_CAP keys: a small work-group each)
   LevelCtl lv[MAX_LEVELS];
   uint32_t nleft[MAX_LEVELS];   // buckets the slot sort handed on, per level
   uint32_t nleft2[MAX_LEVELS];  // of those, buckets the round-based slot sort handed on
@@ -107,7 +108,7 @@ struct Ctl {              // device control block at the start of the workspace
 enum : uint32_t {
   ST_LIST_FULL = 1u,      // a next-level list was full (the bucket was sorted by the fallback)
   ST_FALLBACK = 2u,       // a bucket larger than one work-group was sorted by the fallback
-  ST_BAD_OFFSETS = 4u,    // decreasing segment offsets (segment skipped)
+  ST_BAD_OFFSETS = 4u,    // a segment's offsets decrease, leave [0, total) or exceed max_seg_len (skipped)
 };
 
 // Everything one split level needs.
@@ -152,6 +153,9 @@ struct LevelArgs {
                            // caller's keys; every deeper buffer holds the unsigned images, kin = 0)
   int kout;                // key map of the final output (the caller's key type)
   int iota;                // 1: payload = index in segment, generated (top level)
+  uint32_t use_tab;        // 1: automatically sized segments take p and s from tab_* by size class
+  uint16_t tab_p[33];      // by size class c (lengths in (2^(c-1), 2^c]): buckets
+  uint16_t tab_s[33];      //   and oversampling factor
 };
 
 // ------------------------------------------------------------ helpers
@@ -433,6 +437,14 @@ __global__ void __launch_bounds__(NT) k_plan(LevelArgs a, uint32_t samp_cap) {
         uint32_t q = 2;
         while (q < want && q < a.p_cap) q *= 2;
         uint32_t sv = a.s;
+        if (a.use_tab) {
+          // the tuned p of the segment's size class (never above the target
+          // rule's, which sized the level's bucket arrays; 0 = that rule)
+          uint32_t c = 0;
+          while (c < 32 && (1ull << c) < (uint64_t)d.len) c++;
+          if (a.tab_p[c]) q = min(q, max(2u, (uint32_t)a.tab_p[c]));
+          if (a.tab_s[c]) sv = a.tab_s[c];
+        }
         if ((uint64_t)q * sv > (uint64_t)samp_cap + 1) sv = (samp_cap + 1) / q;
         if ((uint64_t)2 * q * sv >= d.len) sv = (d.len - 1) / (2 * q);
         if (sv < 1) sv = 1;
@@ -1474,19 +1486,35 @@ __global__ void k_init_ctl(Ctl* g) {
   if (threadIdx.x == 0) *g = Ctl{};
 }
 
+// Size classes of the segmented sort below one work-group's capacity:
+// segments of up to WAVE keys are sorted by one wave each (many per
+// work-group, no LDS), up to MID_CAP keys by a work-group with a small LDS
+// footprint (several per CU), the rest by a work-group with the full LDS.
+constexpr uint32_t MID_K = 4;
+constexpr uint32_t MID_CAP = NT * MID_K;
+
 // Segmented input: segments longer than C go to the top level's list, the
-// others to the small list (sorted directly by one work-group each).
+// others to the tiny, mid or small list by length.  A segment that ends
+// before it starts, leaves [0, total) or is longer than maxlen (the bound
+// the plan was made for) is skipped and flagged.
 __global__ void k_seg_init(Ctl* g, const int64_t* off, uint32_t nseg, uint32_t C, SegDesc* top, uint32_t top_cap,
-                           SmallEnt* small, uint64_t seed) {
+                           SmallEnt* small, SmallEnt* tiny, SmallEnt* mid, uint64_t seed, uint64_t total,
+                           uint64_t maxlen) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
     int64_t b = off[i], e = off[i + 1];
-    if (e < b) {
+    if (e < b || b < 0 || (uint64_t)e > total || (uint64_t)(e - b) > maxlen) {
       atomicOr(&g->status, ST_BAD_OFFSETS);
       continue;
     }
     uint64_t len = (uint64_t)(e - b);
     if (len == 0) continue;
-    if (len <= C) {
+    if (len <= WAVE) {
+      uint32_t s = atomicAdd(&g->ntiny, 1u);
+      tiny[s] = SmallEnt{(uint64_t)b, (uint32_t)len, 0};
+    } else if (len <= MID_CAP) {
+      uint32_t s = atomicAdd(&g->nmid, 1u);
+      mid[s] = SmallEnt{(uint64_t)b, (uint32_t)len, 0};
+    } else if (len <= C) {
       uint32_t s = atomicAdd(&g->nsmall, 1u);
       small[s] = SmallEnt{(uint64_t)b, (uint32_t)len, 0};
     } else {
@@ -1513,6 +1541,66 @@ __global__ void __launch_bounds__(NT) k_sort_small_list(Ctl* g, const SmallEnt* 
   SmallEnt e = list[blockIdx.x];
   // an iota payload is the index inside the segment (0-based from e.beg)
   sort_small<KW, VW>((const KT*)src, iota ? nullptr : vsrc, (KT*)out, vout, e.beg, e.len, 0, kind, kind, sm);
+}
+
+// Segments of WAVE < len <= MID_CAP keys: the same LDS radix sort with
+// MID_K keys per thread, whose small LDS lets several work-groups share a CU.
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_sort_mid_list(Ctl* g, const SmallEnt* list, const void* src,
+                                                      const void* vsrc, void* out, void* vout, int kind, int iota) {
+  using KT = typename KeyOf<KW>::T;
+  __shared__ SmallLds<KW, VW, MID_K> sm;
+  const uint32_t nm = g->nmid;
+  for (uint32_t li = blockIdx.x; li < nm; li += gridDim.x) {
+    const SmallEnt e = list[li];
+    if (e.len <= (uint32_t)NT)
+      sort_small_k<KW, VW, 1, MID_K>((const KT*)src, iota ? nullptr : vsrc, (KT*)out, vout, e.beg, e.len, 0, kind,
+                                     kind, sm);
+    else
+      sort_small_k<KW, VW, MID_K, MID_K>((const KT*)src, iota ? nullptr : vsrc, (KT*)out, vout, e.beg, e.len, 0,
+                                         kind, kind, sm);
+  }
+}
+
+// Segments of at most WAVE keys: one wave per segment, one item per lane.
+// A lane's rank is the number of items whose (key, index) is smaller, read
+// lane by lane from the wave (scalar broadcasts, no LDS); every lane then
+// writes its key (and payload) at its rank, which is the stable order.
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_sort_tiny_list(Ctl* g, const SmallEnt* list, const void* src,
+                                                       const void* vsrc, void* out, void* vout, int kind, int iota) {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  const uint32_t nt = g->ntiny;
+  const int l = lane_id();
+  for (uint32_t w = blockIdx.x * (NT / WAVE) + wave_id(); w < nt; w += gridDim.x * (NT / WAVE)) {
+    const SmallEnt e = list[w];
+    const uint32_t len = e.len;
+    const bool in = (uint32_t)l < len;
+    const KT key = in ? ((const KT*)src)[e.beg + l] : KT(0);
+    const KT o = in ? to_ord(key, kind) : ~KT(0);
+    uint32_t rank = 0;
+#pragma unroll
+    for (int j = 0; j < WAVE; j++) {
+      if ((uint32_t)j >= len) break;   // (uniform across the wave)
+      KT oj;
+      if constexpr (KW == 4) {
+        oj = (KT)__builtin_amdgcn_readlane((int)o, j);
+      } else {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)o, j);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(o >> 32), j);
+        oj = ((KT)hi << 32) | lo;
+      }
+      rank += (oj < o || (oj == o && j < l)) ? 1u : 0u;
+    }
+    if (in) {
+      ((KT*)out)[e.beg + rank] = key;
+      if constexpr (VW != 0) {
+        const VT v = (iota || !vsrc) ? (VT)l : ((const VT*)vsrc)[e.beg + l];
+        ((VT*)vout)[e.beg + rank] = v;
+      }
+    }
+  }
 }
 
 template <int KW, int VW>

@@ -28,6 +28,7 @@ SS_MAX_LEVELS = 6
 
 EXPORTS = ("ss_last_error", "ss_workspace_size", "ss_stage_layout", "sample_sort_keys", "sample_sort_pairs",
            "ss_segmented_workspace_size", "segmented_sort", "ss_scatter_grad", "ss_status", "ss_level_stats",
+           "ss_set_tuning", "ss_get_tuning",
            "ss_profile_enable", "ss_profile_kinds", "ss_profile_collect", "ss_profile_report")
 
 
@@ -42,6 +43,12 @@ class StageInfo(ctypes.Structure):
                 ("sample_ord", ctypes.c_uint64), ("sample_tag", ctypes.c_uint64), ("spl_ord", ctypes.c_uint64),
                 ("spl_tag", ctypes.c_uint64), ("counts", ctypes.c_uint64), ("direct", ctypes.c_uint32),
                 ("levels", ctypes.c_uint32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_uint32), ("key_bytes", ctypes.c_uint32), ("val_bytes", ctypes.c_uint32),
+                ("size_class", ctypes.c_uint32),
+                ("p", ctypes.c_uint32), ("s", ctypes.c_uint32), ("tile", ctypes.c_uint32)]
 
 
 class LevelInfo(ctypes.Structure):
@@ -79,6 +86,8 @@ def lib():
         L.ss_scatter_grad.argtypes = [P, P, P, SZ, SZ, I, P]
         L.ss_status.argtypes = [P, P]
         L.ss_level_stats.argtypes = [P, I, ctypes.POINTER(LevelInfo), P]
+        L.ss_set_tuning.argtypes = [ctypes.POINTER(TuneEntry), SZ]
+        L.ss_get_tuning.argtypes = [I, I, I, SZ, PP]
         L.ss_profile_enable.argtypes = [I, I]
         L.ss_profile_kinds.argtypes = [ctypes.c_uint]
         L.ss_profile_collect.argtypes = []

@@ -98,6 +98,7 @@ template <class T>
 inline T __builtin_amdgcn_readfirstlane(T x) {
   return emu_xchg(x, 0);
 }
+inline int __builtin_amdgcn_readlane(int x, int src) { return emu_xchg(x, src); }
 inline uint32_t __builtin_amdgcn_mbcnt_lo(uint32_t m, uint32_t acc) {
   const int l = emu_lane();
   return acc + __builtin_popcount(l >= 32 ? m : (m & ((1u << l) - 1u)));

@@ -186,3 +186,44 @@ def test_int64_index_payload_planned_narrow():
     assert L.ss_segmented_workspace_size(total, nseg, maxlen, N.SS_F32, N.SS_V_IOTA32, None, ctypes.byref(out32)) == 0
     assert L.ss_segmented_workspace_size(total, nseg, maxlen, N.SS_F32, N.SS_V_IOTA64, None, ctypes.byref(out64)) == 0
     assert out64.value - out32.value == ((out32.value + 255) // 256 * 256 - out32.value) + 4 * total
+
+
+def _tuned(form, kt, vt, n):
+    out = N.Params()
+    assert N.lib().ss_get_tuning(form, kt, vt, n, ctypes.byref(out)) == 0, N.last_error()
+    return out.p, out.s, out.tile
+
+
+def test_tuning_table_set_get_restore():
+    L = N.lib()
+    try:
+        assert L.ss_set_tuning(None, 0) == 0
+        # built-in: keys-only int32 at 2^26 takes 4096 buckets
+        assert _tuned(0, N.SS_I32, N.SS_V_NONE, 2**26)[0] == 4096
+        E = (N.TuneEntry * 2)(N.TuneEntry(0, 4, 0, 20, 512, 8, 65536), N.TuneEntry(1, 4, 0, 18, 16, 4, 0))
+        assert L.ss_set_tuning(E, 2) == 0
+        assert _tuned(0, N.SS_I32, N.SS_V_NONE, 2**20) == (512, 8, 65536)
+        assert _tuned(0, N.SS_U32, N.SS_V_NONE, 2**19 + 1) == (512, 8, 65536)     # same class (2^19, 2^20]
+        assert _tuned(0, N.SS_I32, N.SS_V_NONE, 2**19) != (512, 8, 65536)
+        assert _tuned(1, N.SS_I32, N.SS_V_NONE, 2**18)[:2] == (16, 4)
+        assert _tuned(0, N.SS_I32, N.SS_V_B32, 2**20) != (512, 8, 65536)          # other payload width
+        # a 64-bit index payload is tuned as a 4-byte one
+        assert _tuned(0, N.SS_F32, N.SS_V_IOTA64, 2**20) == _tuned(0, N.SS_F32, N.SS_V_B32, 2**20)
+        # an invalid entry is refused and the table stays as it was
+        bad = (N.TuneEntry * 1)(N.TuneEntry(0, 4, 0, 20, 3, 8, 0))
+        assert L.ss_set_tuning(bad, 1) == N.SS_EINVAL
+        assert _tuned(0, N.SS_I32, N.SS_V_NONE, 2**20) == (512, 8, 65536)
+        bad = (N.TuneEntry * 1)(N.TuneEntry(0, 4, 0, 33, 64, 8, 0))
+        assert L.ss_set_tuning(bad, 1) == N.SS_EINVAL
+        bad = (N.TuneEntry * 1)(N.TuneEntry(0, 4, 0, 20, 0, 8, 0))                # p = 0: segmented only
+        assert L.ss_set_tuning(bad, 1) == N.SS_EINVAL
+        # workspace sizes follow the table when prm is NULL
+        out = ctypes.c_size_t()
+        assert L.ss_workspace_size(2**20, N.SS_I32, N.SS_V_NONE, None, ctypes.byref(out)) == 0
+        prm = N.Params(p=512, s=8, sampling=0, stable=1, seed=0x5EED, flags=0, tile=65536)
+        out2 = ctypes.c_size_t()
+        assert L.ss_workspace_size(2**20, N.SS_I32, N.SS_V_NONE, ctypes.byref(prm), ctypes.byref(out2)) == 0
+        assert out.value == out2.value
+    finally:
+        assert L.ss_set_tuning(None, 0) == 0
+    assert _tuned(0, N.SS_I32, N.SS_V_NONE, 2**20) != (512, 8, 65536)

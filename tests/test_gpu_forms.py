@@ -164,3 +164,81 @@ def test_regular_2p20_config():
     np.testing.assert_array_equal(st["counts"], ref["counts"])
     np.testing.assert_array_equal(to_host(out, np.uint32), keys[ref["perm"]])
     assert st["counts"].max() <= oracle.lemma1_bounds(2**20, 64, 8)[1]
+
+
+def test_sortfn_full_shape_64x2p18():
+    """The row sort at its benchmarked shape (64 x 2^18 float32, tie-free):
+    every row's permutation and values equal the oracle's, and the backward
+    equals the oracle's gradient scatter, bit for bit."""
+    rows, cols = 64, 1 << 18
+    x = workloads.tie_free_rows(rows, cols, workloads.seed_for(4))
+    xd = torch.from_numpy(x).cuda().requires_grad_(True)
+    note("SortFn 64 x 2^18 forward")
+    vals, perm = api.sort(xd)
+    torch.cuda.synchronize()
+    want = np.stack([oracle.stable_perm(r) for r in x])
+    np.testing.assert_array_equal(perm.cpu().numpy(), want)
+    np.testing.assert_array_equal(vals.detach().cpu().numpy(), np.take_along_axis(x, want, 1))
+    gy = torch.randn(rows, cols, device="cuda", generator=torch.Generator("cuda").manual_seed(11))
+    note("SortFn 64 x 2^18 backward")
+    vals.backward(gy)
+    np.testing.assert_array_equal(xd.grad.cpu().numpy(), oracle.scatter_grad(gy.cpu().numpy(), want))
+
+
+def test_segmented_log_uniform_2000_graph_tuned():
+    """The batched form at the benchmarked shape, reduced in count: 2,000
+    segments of log-uniform length in [1, 2^20] (~1.5e8 int32 keys), the
+    library's tuned parameters (prm = NULL), captured in a HIP graph and
+    replayed twice; every segment equals the oracle's sort of it."""
+    sizes = workloads.segment_sizes(2000, workloads.seed_for(3, 1))
+    off = workloads.offsets_from_sizes(sizes)
+    total, max_len = int(off[-1]), int(sizes.max())
+    g = np.random.default_rng(6)
+    keys = g.integers(-2**31, 2**31, total, dtype=np.int64).astype(np.int32)
+    kd = torch.from_numpy(keys).cuda()
+    od = torch.from_numpy(off).cuda()
+    ko = torch.empty_like(kd)
+    ws = api._workspace(api.segmented_workspace_size(total, len(sizes), max_len, N.SS_I32, N.SS_V_NONE, None),
+                        kd.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        api.segmented_sort(kd, od, max_len=max_len, total=total, keys_out=ko, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        api.segmented_sort(kd, od, max_len=max_len, total=total, keys_out=ko, ws=ws)
+    want, _, _ = oracle.segmented_sort(keys, off)
+    for rep in range(2):
+        ko.fill_(0)
+        torch.cuda.synchronize()
+        note(f"2000 log-uniform segments, graph replay {rep}")
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ko.cpu().numpy(), want)
+    assert api.status(ws) == ""
+
+
+def test_segment_offsets_outside_the_plan_are_flagged():
+    """A segment that leaves [0, total) or is longer than max_seg_len is
+    skipped by the device and reported by ss_status; the other segments are
+    still sorted."""
+    keys = np.arange(300, 0, -1).astype(np.int32)
+    kd = torch.from_numpy(keys).cuda()
+    ko = torch.zeros_like(kd)
+    # segment 1 ends past total = 200; segment 0 is fine
+    od = torch.tensor([0, 100, 250], dtype=torch.int64, device="cuda")
+    ws = api._workspace(api.segmented_workspace_size(200, 2, 100, N.SS_I32, N.SS_V_NONE, None), kd.device)
+    note("segment past total")
+    api.segmented_sort(kd, od, total=200, max_len=100, keys_out=ko, ws=ws)
+    with pytest.raises(N.SortError, match="segment offsets"):
+        api.status(ws)
+    np.testing.assert_array_equal(ko[:100].cpu().numpy(), np.sort(keys[:100]))
+    # segment 1 is longer than max_seg_len = 60
+    od2 = torch.tensor([0, 50, 200], dtype=torch.int64, device="cuda")
+    ws2 = api._workspace(api.segmented_workspace_size(200, 2, 60, N.SS_I32, N.SS_V_NONE, None), kd.device)
+    note("segment longer than max_seg_len")
+    api.segmented_sort(kd, od2, total=200, max_len=60, keys_out=ko, ws=ws2)
+    with pytest.raises(N.SortError, match="segment offsets"):
+        api.status(ws2)
+    np.testing.assert_array_equal(ko[:50].cpu().numpy(), np.sort(keys[:50]))
