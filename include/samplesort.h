@@ -209,10 +209,18 @@ int ss_get_tuning(int form, int key_type, int val_type, size_t n, ss_params *out
 /* Backward of a row-wise sort y[r, j] = x[r, perm[r, j]]: the gradient goes
  * back through the permutation, grad_x[r, perm[r, j]] = grad_y[r, j].  Each
  * row of perm must be a permutation of 0..row_len-1 (then every grad_x
- * element is written exactly once).  elem_bytes = 2, 4 or 8.  grad_y,
- * grad_x: device [rows, row_len]; perm: device int64 [rows, row_len]. */
+ * element is written exactly once); an index outside [0, row_len) is not
+ * written and is reported by ss_grad_status.  elem_bytes = 2, 4 or 8.
+ * grad_y, grad_x: device [rows, row_len]; perm: device int64 [rows,
+ * row_len]; grad_y and perm 16-byte aligned; rows, row_len < 2^31. */
 int ss_scatter_grad(const void *grad_y, const int64_t *perm, void *grad_x, size_t rows, size_t row_len,
                     int elem_bytes, void *stream);
+
+/* Wait for `stream`, then report whether any ss_scatter_grad call since the
+ * last ss_grad_status met an index outside its row (SS_EDEVICE, and the
+ * flag is cleared) or not (SS_OK).  The flag is one per process and
+ * device, shared by all calls. */
+int ss_grad_status(void *stream);
 
 /* Wait for `stream`, then read the device status word of the last call that
  * used `ws`: SS_OK, or SS_EDEVICE if the device reported a condition (the

@@ -227,6 +227,12 @@ def scatter_grad(grad_y, perm, grad_x=None, stream=None):
     return grad_x
 
 
+def grad_status(stream=None):
+    """Wait for the stream; raise if a scatter_grad call since the last check
+    met a permutation index outside its row."""
+    N.check(N.lib().ss_grad_status(_stream(stream)))
+
+
 def status(ws, stream=None):
     """Wait for the stream and report the device status of the last call on ws."""
     N.check(N.lib().ss_status(_ptr(ws), _stream(stream)))

@@ -7,6 +7,7 @@
 #include "ss_wide.h"
 #include "ss_pairs.h"
 #include "ss_sortfirst.h"
+#include "ss_tuned.h"
 
 #include <hip/hip_runtime.h>
 
@@ -209,9 +210,11 @@ int size_class(uint64_t n) {
   return c;
 }
 
-// Built-in table.  Single arrays, keys only: buckets of ~16K 4-byte keys
-// (p up to 4096), ~8K 8-byte keys (p up to 1024); with a payload p <= 256
-// (the stable ballot split); s = 16.  Segmented: p from the length, s = 8.
+// Built-in table: the measured entries of ss_tuned.h over a rule for the
+// groups no run measured.  Rule: single arrays, keys only, buckets of ~16K
+// 4-byte keys (p up to 4096), ~8K 8-byte keys (p up to 1024); with a
+// payload p <= 256 (the stable ballot split); s = 16.  Segmented: p from
+// the length, s = 8.
 void tune_builtin(TuneTab (&t)[2][2][3]) {
   for (int kw = 0; kw < 2; kw++)
     for (int vw = 0; vw < 3; vw++)
@@ -227,6 +230,12 @@ void tune_builtin(TuneTab (&t)[2][2][3]) {
         t[1][kw][vw].s[c] = 8;
         t[1][kw][vw].tile[c] = 0;
       }
+  for (const auto& e : TUNED) {
+    TuneTab& tt = t[e[0]][e[1] == 8][e[2] == 0 ? 0 : (e[2] == 4 ? 1 : 2)];
+    tt.p[e[3]] = (uint16_t)e[4];
+    tt.s[e[3]] = (uint16_t)e[5];
+    tt.tile[e[3]] = e[6];
+  }
 }
 
 const TuneTab& tune_for(int form, int KW, int VW) {
@@ -1103,6 +1112,7 @@ int sort_common(const void* keys_in, const void* vals_in, void* keys_out, void* 
 
 extern "C" {
 
+
 const char* ss_last_error(void) { return g_err; }
 
 int ss_workspace_size(size_t n, int key_type, int val_type, const ss_params* prm, size_t* bytes_out) {
@@ -1209,33 +1219,59 @@ int segmented_sort(const void* keys_in, const void* vals_in, void* keys_out, voi
   return run_segmented_any(P, (char*)ws, keys_in, vals_in, keys_out, vals_out, d_offsets, as_stream(stream));
 }
 
+// Set by k_scatter_grad when an index falls outside its row; read and
+// cleared by ss_grad_status.
+__device__ uint32_t g_grad_status;
+
 int ss_scatter_grad(const void* grad_y, const int64_t* perm, void* grad_x, size_t rows, size_t row_len,
                     int elem_bytes, void* stream) {
   g_err[0] = 0;
   if (rows == 0 || row_len == 0) return SS_OK;
   if (!grad_y || !perm || !grad_x) return fail(SS_EINVAL, "grad_y, perm and grad_x must be device pointers");
   if (grad_y == grad_x) return fail(SS_EINVAL, "grad_x must not alias grad_y");
-  const uint64_t total = (uint64_t)rows * row_len;
-  const uint32_t grid = grid_of(total, 256, 8192);
+  if (rows >= (1ull << 31) || row_len >= (1ull << 31))
+    return fail(SS_EINVAL, "rows and row_len must be below 2^31");
+  if (((uintptr_t)grad_y | (uintptr_t)perm) % 16)
+    return fail(SS_EINVAL, "grad_y and perm must be 16-byte aligned");
+  const uint32_t per = GRAD_V * GRAD_NT;
+  const uint64_t chunks = cdiv(row_len, per);
+  const uint64_t tiles = chunks * rows;
+  if (tiles >= (1ull << 32)) return fail(SS_EINVAL, "too many elements");
+  if (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8)
+    return fail(SS_EINVAL, "elem_bytes = %d: need 2, 4 or 8", elem_bytes);
+  uint32_t* status = nullptr;
+  HIP_TRY(hipGetSymbolAddress((void**)&status, HIP_SYMBOL(g_grad_status)));
   hipStream_t st = as_stream(stream);
   switch (elem_bytes) {
     case 2:
-      LAUNCH(PK_GRAD, k_scatter_grad<uint16_t>, dim3(grid), dim3(256), 0, st, (const uint16_t*)grad_y, perm,
-                         (uint16_t*)grad_x, (uint64_t)rows, (uint64_t)row_len);
+      LAUNCH(PK_GRAD, k_scatter_grad<uint16_t>, dim3((uint32_t)tiles), dim3(GRAD_NT), 0, st, (const uint16_t*)grad_y,
+             perm, (uint16_t*)grad_x, (uint32_t)rows, (uint32_t)row_len, (uint32_t)chunks, status);
       break;
     case 4:
-      LAUNCH(PK_GRAD, k_scatter_grad<uint32_t>, dim3(grid), dim3(256), 0, st, (const uint32_t*)grad_y, perm,
-                         (uint32_t*)grad_x, (uint64_t)rows, (uint64_t)row_len);
+      LAUNCH(PK_GRAD, k_scatter_grad<uint32_t>, dim3((uint32_t)tiles), dim3(GRAD_NT), 0, st, (const uint32_t*)grad_y,
+             perm, (uint32_t*)grad_x, (uint32_t)rows, (uint32_t)row_len, (uint32_t)chunks, status);
       break;
     case 8:
-      LAUNCH(PK_GRAD, k_scatter_grad<uint64_t>, dim3(grid), dim3(256), 0, st, (const uint64_t*)grad_y, perm,
-                         (uint64_t*)grad_x, (uint64_t)rows, (uint64_t)row_len);
+      LAUNCH(PK_GRAD, k_scatter_grad<uint64_t>, dim3((uint32_t)tiles), dim3(GRAD_NT), 0, st, (const uint64_t*)grad_y,
+             perm, (uint64_t*)grad_x, (uint32_t)rows, (uint32_t)row_len, (uint32_t)chunks, status);
       break;
     default:
       return fail(SS_EINVAL, "elem_bytes = %d: need 2, 4 or 8", elem_bytes);
   }
   LAUNCH_CHECK();
   return SS_OK;
+}
+
+int ss_grad_status(void* stream) {
+  g_err[0] = 0;
+  hipStream_t st = as_stream(stream);
+  HIP_TRY(hipStreamSynchronize(st));
+  uint32_t v = 0, zero = 0;
+  HIP_TRY(hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_grad_status), sizeof v, 0, hipMemcpyDeviceToHost));
+  if (!v) return SS_OK;
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(g_grad_status), &zero, sizeof zero, 0, hipMemcpyHostToDevice));
+  return fail(SS_EDEVICE, "ss_scatter_grad: a permutation index was outside its row (those entries were not "
+                          "written; the flag is now cleared)");
 }
 
 int ss_set_tuning(const ss_tune_entry* entries, size_t count) {

@@ -1628,14 +1628,61 @@ __global__ void k_block_offsets(int64_t* off, uint64_t n, uint32_t p) {
 }
 
 // Backward of a row-wise sort: grad_x[r, perm[r, j]] = grad_y[r, j].
+// Work-group w handles GRAD_V * 256 consecutive elements of one row: the
+// grid is rows x chunks tiles, numbered row-major and mapped to work-groups
+// so that each XCD takes a contiguous range of tiles (whole rows), which
+// keeps every row's scattered writes in one XCD's L2, where they fill whole
+// lines before they are written back.  Each thread loads GRAD_V gradients
+// and GRAD_V indices with vector loads.  An index outside [0, cols) is not
+// written and raises the library's gradient status flag (the rest of the
+// row is still scattered).
+constexpr int GRAD_V = 4;
+constexpr int GRAD_NT = 256;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_scatter_grad(const T* gy, const int64_t* perm, T* gx, uint64_t rows,
-                                                      uint64_t cols) {
-  const uint64_t total = rows * cols;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (uint64_t)gridDim.x * 256) {
-    uint64_t r = i / cols;
-    int64_t pj = perm[i];
-    if (pj >= 0 && (uint64_t)pj < cols) gx[r * cols + (uint64_t)pj] = gy[i];
+__global__ void __launch_bounds__(GRAD_NT) k_scatter_grad(const T* gy, const int64_t* perm, T* gx, uint32_t rows,
+                                                          uint32_t cols, uint32_t chunks, uint32_t* status) {
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t r = tile / chunks, ch = tile - r * chunks;
+  if (r >= rows) return;
+  const uint32_t j0 = ch * (GRAD_V * GRAD_NT) + threadIdx.x * GRAD_V;
+  if (j0 >= cols) return;
+  const uint64_t base = (uint64_t)r * cols;
+  const T* g = gy + base;
+  const int64_t* pr = perm + base;
+  T* out = gx + base;
+  T v[GRAD_V];
+  int64_t q[GRAD_V];
+  // (a row of cols % GRAD_V != 0 ends unaligned: scalar loads at its end)
+  if (j0 + GRAD_V <= cols && (cols % GRAD_V) == 0) {
+    // GRAD_V gradients: 8, 16 or 32 bytes, aligned to their size (the row
+    // length is a multiple of GRAD_V and grad_y is 16-byte aligned)
+    if constexpr (sizeof(T) * GRAD_V == 8) {
+      const uint2 w = *(const uint2*)(g + j0);
+      __builtin_memcpy(v, &w, sizeof v);
+    } else {
+      constexpr int NV = sizeof(T) * GRAD_V / 16;
+      uint4 w[NV];
+#pragma unroll
+      for (int k = 0; k < NV; k++) w[k] = ((const uint4*)(g + j0))[k];
+      __builtin_memcpy(v, w, sizeof v);
+    }
+    const uint4* pv = (const uint4*)(pr + j0);
+    uint4 pp[GRAD_V / 2];
+#pragma unroll
+    for (int k = 0; k < GRAD_V / 2; k++) pp[k] = pv[k];
+    __builtin_memcpy(q, pp, sizeof q);
+#pragma unroll
+    for (int k = 0; k < GRAD_V; k++) {
+      if ((uint64_t)q[k] < cols) out[q[k]] = v[k];
+      else atomicOr(status, 1u);
+    }
+  } else {
+    for (uint32_t j = j0; j < min(j0 + GRAD_V, cols); j++) {
+      const int64_t pj = pr[j];
+      if ((uint64_t)pj < cols) out[pj] = g[j];
+      else atomicOr(status, 1u);
+    }
   }
 }
 

@@ -28,7 +28,7 @@ SS_MAX_LEVELS = 6
 
 EXPORTS = ("ss_last_error", "ss_workspace_size", "ss_stage_layout", "sample_sort_keys", "sample_sort_pairs",
            "ss_segmented_workspace_size", "segmented_sort", "ss_scatter_grad", "ss_status", "ss_level_stats",
-           "ss_set_tuning", "ss_get_tuning",
+           "ss_set_tuning", "ss_get_tuning", "ss_grad_status",
            "ss_profile_enable", "ss_profile_kinds", "ss_profile_collect", "ss_profile_report")
 
 
@@ -85,6 +85,7 @@ def lib():
         L.segmented_sort.argtypes = [P, P, P, P, P, SZ, SZ, SZ, I, I, PP, P, SZ, P]
         L.ss_scatter_grad.argtypes = [P, P, P, SZ, SZ, I, P]
         L.ss_status.argtypes = [P, P]
+        L.ss_grad_status.argtypes = [P]
         L.ss_level_stats.argtypes = [P, I, ctypes.POINTER(LevelInfo), P]
         L.ss_set_tuning.argtypes = [ctypes.POINTER(TuneEntry), SZ]
         L.ss_get_tuning.argtypes = [I, I, I, SZ, PP]

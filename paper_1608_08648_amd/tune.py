@@ -390,13 +390,31 @@ def _fill_classes(entries):
     return out
 
 
+def emit_c(entries, device, path):
+    """Write the measured entries as the C table the library builds in
+    (csrc/ss_tuned.h), so that a fresh process without a cache uses them."""
+    lines = ["// Tuned (p, s, tile) per form, key width, payload width and size class,",
+             f"// measured on {device} by `python -m paper_1608_08648_amd.tune --emit-c <this file>`",
+             "// (classes between and beyond the measured ones take the nearest measured",
+             "// class's bucket size).  Fields: form, key_bytes, val_bytes, size_class, p, s, tile.",
+             "#pragma once", "", "namespace ss {", "", "constexpr uint32_t TUNED[][7] = {"]
+    for e in sorted(entries, key=lambda e: tuple(e[k] for k in _FIELDS)):
+        lines.append("    {" + ", ".join(str(int(e[k])) for k in _FIELDS) + "},")
+    lines += ["};", "", "}  // namespace ss", ""]
+    with open(path, "w") as f:
+        f.write("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=None, help="cache file (default: $SS_TUNE_CACHE or ~/.cache/...)")
     ap.add_argument("--report", default=None, help="also write the report as JSON here")
+    ap.add_argument("--emit-c", default=None, help="also write the table as a C header (the built-in table)")
     args = ap.parse_args()
     entries, report = run(quick=args.quick, path=args.out)
+    if args.emit_c:
+        emit_c(entries, device_key(), args.emit_c)
     if args.report:
         with open(args.report, "w") as f:
             json.dump({"device": device_key(), "entries": entries, "report": report}, f, indent=1)

@@ -242,3 +242,35 @@ def test_segment_offsets_outside_the_plan_are_flagged():
     with pytest.raises(N.SortError, match="segment offsets"):
         api.status(ws2)
     np.testing.assert_array_equal(ko[:50].cpu().numpy(), np.sort(keys[:50]))
+
+
+@pytest.mark.parametrize("nbytes", [2, 4, 8])
+def test_scatter_grad_vector_path(nbytes):
+    """Rows whose length is a multiple of the vector width take the vector
+    loads; several rows per XCD range and a tail of partial chunks."""
+    dt = {2: torch.float16, 4: torch.float32, 8: torch.float64}[nbytes]
+    g = torch.Generator().manual_seed(10 + nbytes)
+    rows, cols = 19, 3076
+    gy = torch.randn(rows, cols, generator=g).to(dt)
+    perm = torch.stack([torch.randperm(cols, generator=g) for _ in range(rows)])
+    got = api.scatter_grad(gy.cuda(), perm.cuda()).cpu()
+    np.testing.assert_array_equal(got.numpy(), oracle.scatter_grad(gy.numpy(), perm.numpy()))
+    api.grad_status()
+
+
+def test_scatter_grad_flags_an_index_outside_the_row():
+    cols = 1024
+    gy = torch.arange(2 * cols, dtype=torch.float32).view(2, cols)
+    perm = torch.stack([torch.randperm(cols), torch.randperm(cols)])
+    bad = perm.clone()
+    j = int((bad[1] == 5).nonzero()[0, 0])
+    bad[1, j] = cols                      # outside the row: not written, flagged
+    api.grad_status()                     # (clears any earlier flag)
+    gx = torch.full((2, cols), -1.0, device="cuda")
+    api.scatter_grad(gy.cuda(), bad.cuda(), grad_x=gx)
+    with pytest.raises(N.SortError, match="outside its row"):
+        api.grad_status()
+    api.grad_status()                     # cleared
+    want = oracle.scatter_grad(gy.numpy(), perm.numpy())
+    want[1, 5] = -1.0
+    np.testing.assert_array_equal(gx.cpu().numpy(), want)
