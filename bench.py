@@ -9,7 +9,8 @@ sort, splitters, classification and counts, the split and the bucket sorts.
 Prints ONE JSON line with Gkeys/s, the roofline of the dominant kernel
 (algorithmic bytes / its HIP-event time, against 8 TB/s HBM), the CPU
 oracle's rate on a bounded sample of the same workload (timed first, on one
-pinned host core, before anything touches the GPU), and -- after the
+pinned host core, before anything touches the GPU), the paper's multi-core
+McRan on the host's cores on the same sample (host_mcran), and -- after the
 headline's timed region -- a "batched" object with the two other forms of
 the metric:
 
@@ -109,6 +110,41 @@ def cpu_baseline(keys, log2n, runs):
             "sample": f"first 2^{int(log2n)} keys of the same input, mean of {runs} runs "
                       f"({t:.2f} s each; fastest {min(ts):.2f} s = {sample.size / min(ts) / 1e9:.5f} Gkeys/s)",
             "pinned_core": core, "host_cpu": _cpu_model(), "host_cpu_count": os.cpu_count()}
+
+
+def host_mcran(keys, log2n, runs):
+    """The paper's multi-core McRan (sort-first: p blocks sorted on t
+    threads, random sample, binary-search split, p-way merge per bucket) on
+    this host's cores: p = 256, the paper's default s = ceil(lg^2 n), on a
+    prefix of the same input.  "paper_8_threads" is the configuration of the
+    paper's measurements (8 threads for step 1, step 5 on one thread; one
+    run); "all_cores" spreads steps 1 and 5 over every core (mean of `runs`,
+    fastest beside it).  A CPU reference point on the same machine, not the
+    target."""
+    import math
+
+    import numpy as np
+
+    from paper_1608_08648_amd import host
+    sample = keys[: min(keys.size, 1 << log2n)]
+    n = sample.size
+    p, s = 256, math.ceil(math.log2(n) ** 2)
+    cores = min(len(os.sched_getaffinity(0)), 64)
+    want = np.sort(sample)
+    res = {"unit": "Gkeys/s", "kind": "McRan (paper Alg. 2 with multi-core step 1), qsort as SomeSort",
+           "sample": f"first 2^{int(log2n)} keys of the same input", "p": p, "s": s, "cores": cores}
+    for key, t, mt, reps in (("all_cores", cores, cores, runs), ("paper_8_threads", 8, 1, 1)):
+        ts, steps, ok = [], None, True
+        for _ in range(reps):
+            y, st = host.mcran_sort(sample, p, s, t, seed=7, merge_threads=mt)
+            ts.append(st["total_s"])
+            steps = st
+            ok = ok and bool(np.array_equal(y, want))
+        res[key] = {"threads": t, "merge_threads": mt, "value": round(n / (sum(ts) / len(ts)) / 1e9, 5),
+                    "fastest": round(n / min(ts) / 1e9, 5), "runs": reps,
+                    "steps_s": {k: round(v, 3) for k, v in steps.items()}, "check": "sorted" if ok else "FAILED"}
+    res["value"] = res["all_cores"]["value"]
+    return res
 
 
 # --------------------------------------------------------------- helpers
@@ -510,9 +546,11 @@ def main():
         keys = workloads.keys_2p26(1 << args.log2n, args.dist, seed, np.int32)
         # the CPU baseline first: one pinned core, before anything touches the GPU
         cpu = None if args.no_cpu else cpu_baseline(keys, args.cpu_log2n, args.cpu_runs)
+        mc = None if args.no_cpu else host_mcran(keys, args.cpu_log2n, args.cpu_runs)
         res, ok = bench_sort(args, keys)
         if cpu is not None:
             res["cpu_baseline"] = cpu
+            res["host_mcran"] = mc
         if not args.no_batched:
             seg, ok1 = bench_segmented(max(2, args.steps // 4), 1)
             ag, ok2 = bench_autograd(max(4, args.steps // 2), 2)
