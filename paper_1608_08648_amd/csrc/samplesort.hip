@@ -283,16 +283,13 @@ uint32_t tab_target(const TuneTab& tab, uint32_t C, uint64_t maxlen, uint32_t ta
 
 void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint64_t maxlen0, uint32_t p0,
                  uint64_t m0, uint64_t est_max0, uint32_t s, uint32_t p_cap, uint32_t tile_req, bool recurse,
-                 LevelsPlan* P, uint32_t cpush0 = 0, const TuneTab* tab = nullptr, uint32_t s_deep = 0) {
-  // levels below a single sort's top level sample at random with s_deep
-  // (the top level's s is regular sampling's r when that level is regular)
-  if (!s_deep) s_deep = s;
+                 LevelsPlan* P, uint32_t cpush0 = 0, const TuneTab* tab = nullptr) {
   const uint32_t C = small_cap(ty.KW, ty.VW);
   // buckets larger than this go one level down when there is a level below
   // (keys only: beyond the slot sort's capacity)
   const uint32_t Cpush = ty.VW == 0 ? slot_cap(ty.KW) : C;
   const uint32_t Cs = sample_cap(ty.KW);
-  double f = spread(p0 ? s_deep : s);
+  double f = spread(s);
   // automatically sized buckets aim at about half of what the bucket sort
   // takes in one work-group (the slot sort for keys only)
   uint32_t target = ty.VW == 0 ? (uint32_t)(0.53 * slot_cap(ty.KW))
@@ -314,7 +311,7 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
   uint64_t est = 0;
   for (int l = 0; l < MAX_LEVELS; l++) {
     LevelPlan& lv = P->lv[l];
-    lv.s = (p0 && l > 0) ? s_deep : s;
+    lv.s = s;
     lv.target = target;
     if (l == 0 && p0) {
       lv.p_cap = p0;
@@ -507,10 +504,7 @@ int plan_single_t(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   }
   // (the wide split's bucket sort takes any size in rounds; a level below
   // pays once buckets would need many rounds)
-  // (regular sampling's s is the paper's r, a small integer: the random
-  // splits below it take at least the oversampling of the tuned defaults)
-  plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp, P->wide ? WIDE_LEVEL_MIN : 0,
-              nullptr, P->regular ? std::max<uint32_t>(prm.s, 8) : prm.s);
+  plan_levels(L, ty, n, 1, n, p, P->m, est, prm.s, 256, prm.tile, recurse, &P->lp, P->wide ? WIDE_LEVEL_MIN : 0);
   // with input == output the wide split's first pass needs a buffer of its
   // own: the stage, or the fine buckets (which a bucket sort of several
   // rounds re-reads while it writes the output)
