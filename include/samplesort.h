@@ -151,6 +151,25 @@ int sample_sort_pairs(const void *keys_in, const void *vals_in, void *keys_out, 
                       size_t n, int key_type, int val_type, const ss_params *prm,
                       void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * keys-only sort of sample_sort_keys with its workspace in a static device
+ * array of ss_noalloc_capacity_bytes() bytes (64 MiB) that the library holds
+ * on every GPU it runs on until the process ends.  No device memory is
+ * allocated and no workspace is passed.  A call whose plan needs more
+ * scratch than the array holds (ss_workspace_size larger than the capacity:
+ * about 2^22 4-byte keys with the tuned parameters) is refused with
+ * SS_EWORKSPACE before anything is enqueued.  Every call on one GPU shares
+ * that GPU's array, so calls that overlap in time on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller;
+ * ss_status and ss_level_stats do not apply to it.  Arguments and results
+ * are those of sample_sort_keys. */
+int sample_sort_keys_noalloc(const void *keys_in, void *keys_out, size_t n, int key_type, const ss_params *prm,
+                             void *stream);
+
+/* Bytes of the static scratch array of sample_sort_keys_noalloc.  Host only. */
+size_t ss_noalloc_capacity_bytes(void);
+
 /* Workspace bytes for segmented_sort: `total` keys in `num_segments`
  * segments, none longer than `max_seg_len` (0 = unknown, taken as total). */
 int ss_segmented_workspace_size(size_t total, size_t num_segments, size_t max_seg_len, int key_type,

@@ -1108,10 +1108,68 @@ int sort_common(const void* keys_in, const void* vals_in, void* keys_out, void* 
   return run_single_any(P, (char*)ws, keys_in, vals_in, keys_out, vals_out, as_stream(stream));
 }
 
+// -------------------------------------------------- no-allocation entry
+//
+// sample_sort_keys_noalloc runs the keys-only sort with its workspace in a
+// static device array instead of a caller-provided buffer.  In host code
+// `scratch` only names the symbol: its device address (one per GPU) comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int scratch_of_current_device(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(SS_EINVAL, "device %d: at most %d devices", dev, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(SS_EHIP, "hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SS_OK;
+}
+
+int sort_noalloc(const void* keys_in, void* keys_out, size_t n, int key_type, const ss_params* prm, void* stream) {
+  g_err[0] = 0;
+  Types ty;
+  int rc = parse_types(key_type, SS_V_NONE, &ty);
+  if (rc) return rc;
+  ss_params p;
+  rc = check_params(prm, &p, ty, n);
+  if (rc) return rc;
+  if (n == 0) return SS_OK;
+  if (!keys_in || !keys_out) return fail(SS_EINVAL, "keys_in and keys_out must be device pointers");
+  const size_t kb = (size_t)ty.KW * n;
+  if (overlap_partial(keys_in, kb, keys_out, kb)) return fail(SS_EINVAL, "inputs and outputs overlap partially");
+  Plan P;
+  rc = plan_single(&P, n, ty, p);
+  if (rc) return rc;
+  if (P.bytes > NOALLOC_SCRATCH_BYTES)
+    return fail(SS_EWORKSPACE, "n = %zu needs %zu bytes of scratch; the static scratch array holds %zu", n, P.bytes,
+                NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  rc = scratch_of_current_device(&ws);
+  if (rc) return rc;
+  return run_single_any(P, (char*)ws, keys_in, nullptr, keys_out, nullptr, as_stream(stream));
+}
+
 }  // namespace
 
 extern "C" {
 
+int sample_sort_keys_noalloc(const void* keys_in, void* keys_out, size_t n, int key_type, const ss_params* prm,
+                             void* stream) {
+  return sort_noalloc(keys_in, keys_out, n, key_type, prm, stream);
+}
+
+size_t ss_noalloc_capacity_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 
 const char* ss_last_error(void) { return g_err; }
 

@@ -28,7 +28,8 @@ SS_MAX_LEVELS = 6
 
 EXPORTS = ("ss_last_error", "ss_workspace_size", "ss_stage_layout", "sample_sort_keys", "sample_sort_pairs",
            "ss_segmented_workspace_size", "segmented_sort", "ss_scatter_grad", "ss_status", "ss_level_stats",
-           "ss_set_tuning", "ss_get_tuning", "ss_grad_status",
+           "ss_set_tuning", "ss_get_tuning", "ss_grad_status", "sample_sort_keys_noalloc",
+           "ss_noalloc_capacity_bytes",
            "ss_profile_enable", "ss_profile_kinds", "ss_profile_collect", "ss_profile_report")
 
 
@@ -86,6 +87,8 @@ def lib():
         L.ss_scatter_grad.argtypes = [P, P, P, SZ, SZ, I, P]
         L.ss_status.argtypes = [P, P]
         L.ss_grad_status.argtypes = [P]
+        L.sample_sort_keys_noalloc.argtypes = [P, P, SZ, I, PP, P]
+        L.ss_noalloc_capacity_bytes.argtypes = []
         L.ss_level_stats.argtypes = [P, I, ctypes.POINTER(LevelInfo), P]
         L.ss_set_tuning.argtypes = [ctypes.POINTER(TuneEntry), SZ]
         L.ss_get_tuning.argtypes = [I, I, I, SZ, PP]
@@ -97,6 +100,7 @@ def lib():
         for name in EXPORTS:
             if name != "ss_last_error":
                 getattr(L, name).restype = I
+        L.ss_noalloc_capacity_bytes.restype = SZ
         _lib = L
     return _lib
 
