@@ -93,12 +93,12 @@ struct ProfScope {
       return;
     slot = g_prof.used++;
     g_prof.kind[slot] = k;
-    hipEventRecord(g_prof.ev[2 * slot], st);
+    (void)hipEventRecord(g_prof.ev[2 * slot], st);
   }
   ~ProfScope() {
     if (slot < 0) return;
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    if (slot < (int)g_prof.kind.size()) hipEventRecord(g_prof.ev[2 * slot + 1], st);
+    if (slot < (int)g_prof.kind.size()) (void)hipEventRecord(g_prof.ev[2 * slot + 1], st);
   }
 };
 #define LAUNCH(kind, ...)                 \
@@ -260,8 +260,6 @@ struct LevelsPlan {
   int nlev = 0;
   LevelPlan lv[MAX_LEVELS];
   bool big_sample = false;  // top level sample larger than one work-group (single segment only)
-  int merge_passes = 0;
-  size_t o_sord2 = 0, o_stag2 = 0;
 };
 
 // Shapes of the split levels.  Level 0 either has one segment with given p0
@@ -346,14 +344,7 @@ void plan_levels(Layout& L, const Types& ty, uint64_t N, uint64_t seg_cap0, uint
     lv.o_part = L.take(4 * (cdiv(std::max<uint64_t>(lv.hist_cap, 1), SCAN_BLOCK) + 1));
     lv.o_left = L.take(sizeof(SmallEnt) * std::max<uint64_t>(lv.bkt_cap, 1));
     lv.o_left2 = L.take(sizeof(SmallEnt) * std::max<uint64_t>(lv.bkt_cap, 1));
-    if (l == 0 && p0 && m0 > Cs) {
-      P->big_sample = true;
-      P->merge_passes = 0;
-      const uint64_t ch = sample_chunk(ty.KW);
-      while ((ch << P->merge_passes) < m0) P->merge_passes++;
-      P->o_sord2 = L.take((size_t)ty.KW * m0);
-      P->o_stag2 = L.take(4 * m0);
-    }
+    if (l == 0 && p0 && m0 > Cs) P->big_sample = true;
     P->nlev = l + 1;
     // the top level of a single sort has a caller-chosen p, so its buckets
     // may well exceed the slot sort; deeper levels pick p for the target
@@ -683,10 +674,6 @@ LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void*
   a.vtmp = vtmp;
   a.s_ord = ws + lv.o_sord;
   a.s_tag = (uint32_t*)(ws + lv.o_stag);
-  if (l == 0 && P.lp.big_sample) {
-    a.s_ord2 = ws + P.lp.o_sord2;
-    a.s_tag2 = (uint32_t*)(ws + P.lp.o_stag2);
-  }
   a.tree = ws + lv.o_tree;
   a.tree_tag = lv.o_ttag ? (uint32_t*)(ws + lv.o_ttag) : nullptr;
   a.hist = (uint32_t*)(ws + lv.o_hist);
@@ -838,8 +825,11 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
     const LevelPlan& lv = P.lp.lv[l];
     LevelArgs a = level_args(P, ws, l, in, vin, out, vout);
     const int exp = (P.exp && l == 0) ? 1 : 0;
-    LAUNCH(PK_PLAN, k_plan, dim3(1), dim3(NT), 0, st, a, Cs);
-    LAUNCH_CHECK();
+    // (the top level of a single sort is planned by k_init_single)
+    if (l > 0 || P.segmented) {
+      LAUNCH(PK_PLAN, k_plan, dim3(1), dim3(NT), 0, st, a, Cs);
+      LAUNCH_CHECK();
+    }
     // sample
     if (l == 0 && P.regular) {
       const uint32_t S = P.s * P.p_eff;
@@ -871,23 +861,12 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
     }
     if (sample_done) {
     } else if (l == 0 && P.lp.big_sample) {
+      // sorted chunks, then every record's rank among all of them: the
+      // splitters go straight to the tree
       const uint32_t ch = sample_chunk(KW);
       LAUNCH(PK_SAMPLE_SORT, k_sample_chunk_sort<KW>, dim3((uint32_t)cdiv(P.m, ch)), dim3(NT), 0, st, a);
       LAUNCH_CHECK();
-      void* so = a.s_ord;
-      uint32_t* stg = a.s_tag;
-      void* so2 = a.s_ord2;
-      uint32_t* st2 = a.s_tag2;
-      for (int ps = 0; ps < P.lp.merge_passes; ps++) {
-        uint32_t run = ch << ps;
-        LAUNCH(PK_SAMPLE_MERGE, k_sample_merge<KW>, dim3((uint32_t)cdiv(P.m, MERGE_TILE)), dim3(NT), 0, st,
-                           (const void*)so, (const uint32_t*)stg, so2, st2, (uint32_t)P.m, run);
-        LAUNCH_CHECK();
-        std::swap(so, so2);
-        std::swap(stg, st2);
-      }
-      LAUNCH(PK_TREE, k_build_tree<KW>, dim3(grid_of(std::max<uint64_t>(P.m, P.p_eff), 256, 1024)), dim3(256), 0,
-                         st, a, (const void*)so, (const uint32_t*)stg, exp);
+      LAUNCH(PK_SAMPLE_MERGE, k_sample_rank<KW>, dim3((uint32_t)cdiv(P.m, 256)), dim3(256), 0, st, a, exp);
     } else {
       LAUNCH(PK_SAMPLE_SORT, k_sample_sort_wg<KW>, dim3(lv.seg_cap), dim3(NT), 0, st, a, exp);
     }
@@ -1017,7 +996,7 @@ int run_single(const Plan& P, char* ws, const void* in, const void* vin, void* o
     if (rc) return rc;
   }
   LAUNCH(PK_INIT, k_init_single, dim3(1), dim3(64), 0, st, g, (SegDesc*)(ws + P.lp.lv[0].o_segs), (uint64_t)P.n,
-                     P.p_eff, (uint32_t)P.m, P.stride, P.prm.seed);
+                     P.p_eff, (uint32_t)P.m, P.stride, P.prm.seed, P.lp.lv[0].tile);
   LAUNCH_CHECK();
   return run_levels<KW, VW>(P, ws, in, vin, out, vout, st);
 }
@@ -1374,7 +1353,7 @@ int ss_profile_enable(int on, int max_launches) {
   g_err[0] = 0;
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on.store(false, std::memory_order_release);
-  for (hipEvent_t e : g_prof.ev) hipEventDestroy(e);
+  for (hipEvent_t e : g_prof.ev) (void)hipEventDestroy(e);
   g_prof.reset();
   if (!on) return SS_OK;
   if (max_launches < 1 || max_launches > (1 << 20)) return fail(SS_EINVAL, "max_launches out of range");

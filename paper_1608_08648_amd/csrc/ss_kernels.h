@@ -27,7 +27,6 @@ constexpr int MAX_LEVELS = 6;    // split levels including the top one
 constexpr int SCAN_ITEMS = 8;    // scan: items per thread
 constexpr int SCAN_BLOCK = NT * SCAN_ITEMS;
 constexpr int MERGE_V = 4;       // merge: outputs per thread
-constexpr int MERGE_TILE = NT * MERGE_V;
 
 template <int KW> struct KeyOf;
 template <> struct KeyOf<4> { using T = uint32_t; };
@@ -130,8 +129,6 @@ struct LevelArgs {
   void* vtmp;
   void* s_ord;             // sample key images (KW bytes each)
   uint32_t* s_tag;         // sample tags
-  void* s_ord2;            // second sample buffer (merge passes)
-  uint32_t* s_tag2;
   void* tree;              // splitter trees
   uint32_t* tree_tag;      // tags of the tree (8-byte keys)
   uint32_t* hist;          // counts, then offsets (in place)
@@ -641,7 +638,7 @@ __global__ void __launch_bounds__(NT) k_sample_sort_wg(LevelArgs a, int export_s
   else sample_sort_one<KW, KM>(a, d, sm, exp);
 }
 
-// Large top-level sample (one segment): chunk sorts, merges, tree.
+// Large top-level sample (one segment): chunk sorts (then k_sample_rank).
 template <int KW>
 __global__ void __launch_bounds__(NT) k_sample_chunk_sort(LevelArgs a) {
   __shared__ SampleLds<KW> sm;
@@ -659,42 +656,56 @@ __global__ void __launch_bounds__(NT) k_sample_chunk_sort(LevelArgs a) {
   (void)sizeof(KT);
 }
 
-// Stable merge of sorted runs of length `run` of the sample: (ord, tag) records.
+// Sorted chunks of a large sample to splitters in one pass: the rank of a
+// record among all m records is its index in its own (sorted) chunk plus,
+// for every other chunk, the number of that chunk's records before it in
+// (ord, tag) order -- records of earlier chunks that equal it count as
+// before it, those of later chunks as after, so equal records (a position
+// drawn twice) still get distinct ranks.  A record whose 1-based rank is a
+// multiple of the stride below p * stride is splitter rank / stride (step
+// 3) and goes to its slot of the implicit tree; with the stage export on
+// every record is also written at its rank.
 template <int KW>
-__global__ void __launch_bounds__(NT) k_sample_merge(const void* sord, const uint32_t* stag, void* dord,
-                                                     uint32_t* dtag, uint32_t m, uint32_t run) {
+__global__ void __launch_bounds__(256) k_sample_rank(LevelArgs a, int export_stages) {
   using KT = typename KeyOf<KW>::T;
-  const KT* so = (const KT*)sord;
-  KT* dk = (KT*)dord;
-  uint64_t o0 = (uint64_t)blockIdx.x * MERGE_TILE;
-  if (o0 >= m) return;
-  uint64_t pb = (o0 / (2ull * run)) * (2ull * run);
-  uint64_t la = (m - pb) < run ? (m - pb) : run;
-  uint64_t lb = (m - pb - la) < run ? (m - pb - la) : run;
-  uint64_t tot = la + lb;
-  uint64_t d = o0 - pb + (uint64_t)threadIdx.x * MERGE_V;
-  if (d >= tot) return;
-  auto less = [](KT ak, uint32_t at, KT bk, uint32_t bt) { return ak < bk || (ak == bk && at < bt); };
-  const KT* A = so + pb;
-  const uint32_t* At = stag + pb;
-  const KT* B = A + la;
-  const uint32_t* Bt = At + la;
-  uint64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
-  while (lo < hi) {
-    uint64_t mid = (lo + hi) / 2;
-    uint64_t bj = d - 1 - mid;
-    if (!less(B[bj], Bt[bj], A[mid], At[mid])) lo = mid + 1;  // A[mid] <= B[bj]
-    else hi = mid;
+  constexpr uint32_t C = SampleChunk<KW>::C;
+  const SegDesc d = a.segs[0];
+  const uint32_t g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= d.m) return;
+  const KT* so = (const KT*)a.s_ord + d.samp_off;
+  const uint32_t* st = a.s_tag + d.samp_off;
+  const KT k = so[g];
+  const uint32_t tg = st[g];
+  const uint32_t c = g / C, nch = (d.m + C - 1) / C;
+  uint32_t rank = g - c * C;
+  for (uint32_t j = 0; j < nch; j++) {
+    if (j == c) continue;
+    const uint32_t b = j * C, len = min(C, d.m - b);
+    const bool le = j < c;                    // count records <= (k, tg), else < (k, tg)
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      const KT ok = so[b + mid];
+      const uint32_t ot = st[b + mid];
+      const bool before = ok < k || (ok == k && (le ? ot <= tg : ot < tg));
+      if (before) lo = mid + 1;
+      else hi = mid;
+    }
+    rank += lo;
   }
-  uint64_t i = lo, j = d - lo;
-  for (int v = 0; v < MERGE_V && d + v < tot; v++) {
-    bool takeA;
-    if (i >= la) takeA = false;
-    else if (j >= lb) takeA = true;
-    else takeA = !less(B[j], Bt[j], A[i], At[i]);
-    uint64_t o = pb + d + v;
-    if (takeA) { dk[o] = A[i]; dtag[o] = At[i]; i++; }
-    else { dk[o] = B[j]; dtag[o] = Bt[j]; j++; }
+  const bool exp = export_stages != 0;
+  if (exp) {
+    a.exp_smp_ord[rank] = (uint64_t)k;
+    a.exp_smp_tag[rank] = tg;
+  }
+  const uint32_t r1 = rank + 1;
+  if (r1 % d.stride == 0) {
+    const uint32_t r = r1 / d.stride;         // splitter rank, 1-based
+    if (r >= 1 && r < d.p) {
+      const uint32_t z = __builtin_ctz(r);
+      const uint32_t slot = (1u << (d.lgp - 1 - z)) + (r >> (z + 1));
+      put_tree<KW>(a, d, slot, k, tg, exp);
+    }
   }
 }
 
@@ -1465,20 +1476,33 @@ __global__ void __launch_bounds__(NT) k_bucket_leftover_keys(LevelArgs a, int li
 
 // ------------------------------------------------- entry kernels
 
-// Zero the control block and write the single top-level segment.
+// Zero the control block and write the single top-level segment, planned
+// (the offsets and totals the level-planning kernel would give one segment
+// of n keys split into p buckets over tiles of `tile` keys).
 __global__ void k_init_single(Ctl* g, SegDesc* segs, uint64_t n, uint32_t p, uint32_t m, uint32_t stride,
-                              uint64_t seed) {
+                              uint64_t seed, uint32_t tile) {
   if (threadIdx.x == 0) {
     *g = Ctl{};
-    g->lv[0].nsegs = 1;
     SegDesc d = {};
     d.beg = 0;
     d.len = (uint32_t)n;
     d.p = p;
+    d.lgp = 31 - __clz(p);
     d.m = m;
     d.stride = stride;
     d.seed = seed;
+    d.ntiles = (uint32_t)((n + tile - 1) / tile);
     segs[0] = d;
+    LevelCtl& c = g->lv[0];
+    c.nsegs = 1;
+    c.total_samples = m;
+    c.total_tiles = d.ntiles;
+    c.total_buckets = p;
+    c.total_tree = p;
+    c.total_hist = (uint64_t)p * d.ntiles;
+    c.max_m = m;
+    c.keys = n;
+    c.bucket_keys = 0;
   }
 }
 

@@ -191,3 +191,19 @@ def test_wide_small_layout_many_rounds(in_place):
         assert st["counts"].max() > 2 * (16000 - 256)   # three rounds or more
         got = out.cpu().numpy()
     np.testing.assert_array_equal(got, _sorted_by_oracle(keys))
+
+
+@pytest.mark.parametrize("offset", [1, 2, 3])
+def test_wide_unaligned_input(offset):
+    """Keys starting 4, 8 or 12 bytes past a 16-byte boundary (a view into a
+    larger tensor) take the count pass's one-key-at-a-time loads; the result
+    is the same bit-exact sort."""
+    n = (1 << 21) + 777
+    keys = workloads.keys_2p26(n + offset, "gaussian", workloads.seed_for(5, 9), np.int32)
+    big = torch.from_numpy(keys).cuda()
+    kd = big[offset:]
+    assert kd.data_ptr() % 16 != 0
+    prm = api.params(p=2048, s=16, seed=5)
+    note(f"wide unaligned offset={offset}")
+    out = api.sort_keys(kd, prm)
+    np.testing.assert_array_equal(out.cpu().numpy(), _sorted_by_oracle(keys[offset:]))
