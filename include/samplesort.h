@@ -70,6 +70,9 @@ enum { SS_RANDOM = 0,   /* Alg. 2: p*s-1 keys drawn uniformly (with replacement)
                                    payload only (SS_EINVAL otherwise); no level below.  Without
                                    the flag the keys are classified and moved unsorted (the
                                    split-first organisation, the default). */
+#define SS_F_SF_MERGE      32u  /* with SS_F_SORT_FIRST: step 5 merges each bucket's p runs (the
+                                   paper's merging, lg p pairwise rounds in LDS) instead of
+                                   gathering them and sorting the bucket */
 
 /* return codes */
 enum { SS_OK = 0, SS_EINVAL = -1, SS_EWORKSPACE = -2, SS_EHIP = -3, SS_EDEVICE = -4 };

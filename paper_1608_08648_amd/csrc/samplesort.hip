@@ -804,10 +804,15 @@ int run_sort_first(const Plan& P, char* ws, LevelArgs a, void* out, int exp, hip
   f.lds_keys = bmax <= SF_LDS_KEYS ? (uint32_t)bmax : 0u;
   LAUNCH(PK_SF_SEARCH, k_sf_search, dim3(f.p), dim3(SF_NT), 4 * (size_t)f.lds_keys, st, f);
   LAUNCH_CHECK();
-  LAUNCH(PK_SF_GATHER, k_sf_gather, dim3(f.p), dim3(SF_GNT), 0, st, f, exp ? a.exp_counts : nullptr);
-  LAUNCH_CHECK();
   a.dst = f.stage;
   a.out = out;
+  if (P.prm.flags & SS_F_SF_MERGE) {
+    LAUNCH(PK_BUCKET_SORT, k_sf_merge, dim3(f.p), dim3(SFM_NT), 0, st, a, f, exp ? a.exp_counts : nullptr);
+    LAUNCH_CHECK();
+    return SS_OK;
+  }
+  LAUNCH(PK_SF_GATHER, k_sf_gather, dim3(f.p), dim3(SF_GNT), 0, st, f, exp ? a.exp_counts : nullptr);
+  LAUNCH_CHECK();
   if (wide_small_rounds(P.n, f.p, P.s))
     LAUNCH(PK_BUCKET_SORT, (k_sf_bucket<WIDE_SCAP, WIDE_SLG>), dim3(f.p), dim3(WIDE_BNT), 0, st, a, f);
   else

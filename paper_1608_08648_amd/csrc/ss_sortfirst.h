@@ -8,9 +8,11 @@
 //   step 4  every splitter is placed in every sorted block by binary search
 //           (the alternative the analysis of step 4 gives to merging), which
 //           cuts block k into the runs X_{k,j};
-//   step 5  bucket j gathers its p runs X_{0,j} .. X_{p-1,j} (in block order)
-//           and sorts them in LDS with the round-based slot sort; the
-//           concatenation of the buckets is the output.
+//   step 5  bucket j is formed from its p runs X_{0,j} .. X_{p-1,j}: merged
+//           pairwise (k_sf_merge, SS_F_SF_MERGE: the merging the paper
+//           states), or gathered in block order and sorted in LDS with the
+//           round-based slot sort (the default); the concatenation of the
+//           buckets is the output.
 // Keys compare as (ord(key), global index), the same total order as the
 // split-first classification, so bucket j holds exactly the keys that
 // classification puts in bucket j.
@@ -160,6 +162,139 @@ __global__ void __launch_bounds__(WIDE_BNT) k_sf_bucket(LevelArgs a, SfArgs f) {
       a.left[k] = SmallEnt{e.x, e.y, j};
     }
   }
+}
+
+// Step 5 as the paper states it: bucket j is the merge of its p runs
+// X_{0,j} .. X_{p-1,j}.  One work-group per bucket merges neighbouring
+// groups of runs pairwise, lg p rounds: in round r groups of 2^r runs
+// become groups of 2^(r+1).  Buckets of up to SFM_CAP keys are merged in
+// LDS; larger ones between the stage and the output (both in global
+// memory, ping-pong), the last round writing the output.  In a round each
+// thread produces consecutive outputs: it finds the pair its first output
+// falls in, splits that pair's merge path at its output (a binary search
+// on the diagonal, the first group winning ties) and merges sequentially
+// from there, moving on to the next pair when one ends.
+constexpr int SFM_NT = 1024;
+constexpr uint32_t SFM_CAP = 16384;            // keys a bucket may have to be merged in LDS
+
+struct SfMergeLds {
+  uint32_t buf[2][SFM_CAP];      // (buf[1] holds the runs' block starts until the first round)
+  uint32_t off[SF_PMAX + 1];     // start of run k in the bucket (off[p] = bucket size)
+  uint32_t red[2 * (SFM_NT / WAVE)];
+};
+static_assert(SF_PMAX <= SFM_CAP, "run starts fit the second buffer");
+
+// One merge round over the bucket: groups of w runs in `in` -> groups of 2w
+// in `out` (outputs [e0, e1) of this thread); `last` converts to key bits.
+__device__ __forceinline__ void sf_merge_round(const uint32_t* in, uint32_t* out, const uint32_t* off, uint32_t p,
+                                               uint32_t w, uint32_t e0, uint32_t e1, bool last, int kind) {
+  auto run_of = [&](uint32_t e) {                // last run whose start is <= e
+    uint32_t lo = 0, hi = p;
+    while (hi - lo > 1) {
+      const uint32_t m = (lo + hi) >> 1;
+      if (off[m] <= e) lo = m;
+      else hi = m;
+    }
+    return lo;
+  };
+  uint32_t e = e0;
+  while (e < e1) {
+    const uint32_t q = run_of(e) / (2 * w);
+    const uint32_t ra = 2 * q * w, rm = min(p, ra + w), rz = min(p, ra + 2 * w);
+    const uint32_t pa = off[ra], pm = off[rm], pz = off[rz];
+    const uint32_t la = pm - pa, lb = pz - pm, d = e - pa;
+    // merge path: i elements from the first group, d - i from the second
+    uint32_t lo = d > lb ? d - lb : 0, hi = min(d, la);
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (in[pa + mid] <= in[pm + d - 1 - mid]) lo = mid + 1;   // (the first group wins ties)
+      else hi = mid;
+    }
+    uint32_t i = lo, k = d - lo;
+    const uint32_t stop = min(e1, pz);
+    for (; e < stop; e++) {
+      const bool takeA = k >= lb || (i < la && in[pa + i] <= in[pm + k]);
+      const uint32_t v = takeA ? in[pa + i] : in[pm + k];
+      out[e] = last ? from_ord(v, kind) : v;
+      if (takeA) i++;
+      else k++;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(SFM_NT) k_sf_merge(LevelArgs a, SfArgs f, uint64_t* exp_counts) {
+  __shared__ SfMergeLds sm;
+  const uint32_t j = blockIdx.x, p = f.p;
+  if (j >= p) return;
+  const int t = threadIdx.x;
+  uint32_t* src = sm.buf[1];     // start of run k in the sorted blocks
+  // run table (as in the gather): lengths, their scan, the bucket's start
+  const uint32_t per = (p + SFM_NT - 1) / SFM_NT;
+  const uint32_t k0 = min(p, (uint32_t)t * per), k1 = min(p, k0 + per);
+  uint32_t cnt = 0, below = 0;
+  for (uint32_t k = k0; k < k1; k++) {
+    const uint32_t* row = f.pos + (uint64_t)k * (p + 1);
+    const uint32_t ra = row[j], rb = row[j + 1];
+    src[k] = (uint32_t)sf_block_start(f.n, p, k) + ra;
+    sm.off[k] = rb - ra;
+    cnt += rb - ra;
+    below += ra;
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan<SFM_NT>(cnt, sm.red, &tot);
+  __syncthreads();
+  for (uint32_t k = k0; k < k1; k++) {
+    const uint32_t l = sm.off[k];
+    sm.off[k] = run;
+    run += l;
+  }
+  if (t == 0) sm.off[p] = tot;
+  uint32_t start;
+  block_excl_scan<SFM_NT>(below, sm.red, &start);
+  __syncthreads();
+  if (t == 0) {
+    f.bkt[j] = make_uint2(start, tot);
+    if (exp_counts) exp_counts[j] = tot;
+  }
+  auto run_of = [&](uint32_t e) {
+    uint32_t lo = 0, hi = p;
+    while (hi - lo > 1) {
+      const uint32_t m = (lo + hi) >> 1;
+      if (sm.off[m] <= e) lo = m;
+      else hi = m;
+    }
+    return lo;
+  };
+  uint32_t rounds = 0;
+  while ((1u << rounds) < p) rounds++;
+  const bool lds = tot <= SFM_CAP;
+  // the runs, in block order, as ord keys: in LDS, or in global memory
+  // where an odd number of rounds then ends in the output
+  uint32_t* g0 = (rounds & 1) ? f.stage + start : (uint32_t*)a.out + start;
+  uint32_t* g1 = (rounds & 1) ? (uint32_t*)a.out + start : f.stage + start;
+  uint32_t* b0 = lds ? sm.buf[0] : g0;
+  for (uint32_t e = t; e < tot; e += SFM_NT) {
+    const uint32_t r = run_of(e);
+    b0[e] = to_ord(f.bkeys[src[r] + (e - sm.off[r])], f.kind);
+  }
+  __syncthreads();
+  const uint32_t K = (tot + SFM_NT - 1) / SFM_NT;
+  const uint32_t e0 = min(tot, (uint32_t)t * K), e1 = min(tot, e0 + K);
+  uint32_t* bufs[2] = {b0, lds ? sm.buf[1] : g1};
+  for (uint32_t r = 0; r < rounds; r++) {
+    const bool last = !lds && r + 1 == rounds;
+    sf_merge_round(bufs[r & 1], bufs[(r + 1) & 1], sm.off, p, 1u << r, e0, e1, last, f.kind);
+    __syncthreads();
+  }
+  if (lds) {
+    const uint32_t* res = bufs[rounds & 1];
+    uint32_t* out = (uint32_t*)a.out + start;
+    for (uint32_t e = t; e < tot; e += SFM_NT) out[e] = from_ord(res[e], f.kind);
+  } else if (rounds == 0) {
+    uint32_t* out = (uint32_t*)a.out + start;   // (p = 1 does not occur: one run is the bucket)
+    for (uint32_t e = t; e < tot; e += SFM_NT) out[e] = from_ord(b0[e], f.kind);
+  }
+  if (t == 0) atomicAdd((unsigned long long*)&a.ctl->bucket_keys, (unsigned long long)tot);
 }
 
 }  // namespace ss

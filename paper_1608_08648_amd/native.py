@@ -21,6 +21,7 @@ SS_F_FORCE_PIPELINE = 2
 SS_F_NO_RECURSION = 4
 SS_F_NO_WIDE = 8
 SS_F_SORT_FIRST = 16
+SS_F_SF_MERGE = 32
 # return codes
 SS_OK, SS_EINVAL, SS_EWORKSPACE, SS_EHIP, SS_EDEVICE = 0, -1, -2, -3, -4
 SS_P_MAX = 4096

@@ -127,3 +127,54 @@ def test_sort_first_small_inputs(n, p, s, mode):
     ref = oracle.stages(keys, pe, s, mode, 19)
     np.testing.assert_array_equal(st["counts"], ref["counts"])
     np.testing.assert_array_equal(to_host(out, np.uint32), keys[ref["perm"]])
+
+
+SFM = SF | N.SS_F_SF_MERGE
+
+
+@pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS)
+def test_sort_first_merge_six_distributions(dist):
+    """Step 5 as the paper states it (SS_F_SF_MERGE: each bucket's p runs
+    merged pairwise in lg p rounds): 2^22 + 12345 int32 keys in each
+    distribution, p = 1024, s = 8, bit-exact."""
+    n = (1 << 22) + 12345
+    keys = workloads.keys_2p26(n, dist, workloads.seed_for(6, workloads.DISTRIBUTIONS.index(dist)), np.int32)
+    kd = torch.from_numpy(keys).cuda()
+    prm = api.params(p=1024, s=8, seed=72, flags=SFM)
+    note(f"sort-first merge {dist} n={n}")
+    out = api.sort_keys(kd, prm)
+    np.testing.assert_array_equal(out.cpu().numpy(), _sorted_by_oracle(keys))
+
+
+@pytest.mark.parametrize("mode,p,s", [(oracle.RANDOM, 256, 4), (oracle.REGULAR, 256, 4), (oracle.RANDOM, 4096, 2),
+                                      (oracle.RANDOM, 2, 1)])
+def test_sort_first_merge_counts_and_large_buckets(mode, p, s):
+    """Bucket counts equal the oracle's; p = 256 on 2^20 keys gives buckets
+    around 4K keys, and p = 2 buckets of 2^19 keys, past the merge's LDS
+    (gathered and sorted by the leftover sort instead)."""
+    n = 1 << 20
+    keys = workloads.uniform_u32(n, workloads.seed_for(0) + 31 + p)
+    keys[::5] = keys[1]
+    kd, kt = to_dev(keys)
+    sampling = "regular" if mode == oracle.REGULAR else "random"
+    prm = api.params(p=p, s=s, seed=5, sampling=sampling, flags=SFM)
+    note(f"sort-first merge stages mode={mode} p={p} s={s}")
+    out, st, info = api.stages(kd, prm, key_type=kt)
+    pe = oracle.p_eff(n, p, s, mode)
+    assert info.p_eff == pe
+    ref = oracle.stages(keys, pe, s, mode, 5)
+    np.testing.assert_array_equal(st["counts"], ref["counts"])
+    np.testing.assert_array_equal(to_host(out, np.uint32), keys[ref["perm"]])
+
+
+def test_sort_first_merge_full_size_in_place():
+    """2^26 int32 keys, p = 4096, s = 16, step 5 by merging, in place."""
+    keys = workloads.keys_2p26(2**26, "uniform", workloads.seed_for(1, 0), np.int32)
+    want = keys[oracle.stable_perm(keys)]
+    kd = torch.from_numpy(keys).cuda()
+    prm = api.params(p=4096, s=16, seed=1234, flags=SFM)
+    ws = api._workspace(api.workspace_size(2**26, N.SS_I32, N.SS_V_NONE, prm), kd.device)
+    note("sort-first merge 2^26 p=4096 in place")
+    api.sort_keys(kd, prm, out=kd, ws=ws)
+    np.testing.assert_array_equal(kd.cpu().numpy(), want)
+    assert api.status(ws) == ""
