@@ -15,6 +15,8 @@ gcc).  This module only marshals numpy arrays to it:
 * :func:`p_eff`, :func:`splitmix64`, :func:`lemma1_bounds` -- the parameter
   rule, the counter-based generator behind random sampling, and the bucket
   bound of Lemma 1.
+* :func:`stable_perm_bytes` -- the stable order of fixed-width byte strings
+  in memcmp order (the paper's 32-byte string keys, Section 3).
 """
 import ctypes
 import os
@@ -70,6 +72,8 @@ def _bind(so_path):
     lib.orc_ord_array.restype = None
     lib.orc_lemma1.argtypes = [U64, ctypes.c_uint32, ctypes.c_uint32, P, P]
     lib.orc_lemma1.restype = None
+    lib.orc_stable_sort_bytes.argtypes = [P, U64, ctypes.c_uint32, P]
+    lib.orc_stable_sort_bytes.restype = ctypes.c_int
     return lib
 
 
@@ -165,6 +169,16 @@ class Oracle:
         return {"sample_ord": so, "sample_tag": st, "spl_ord": po, "spl_tag": pt,
                 "counts": cnt.astype(np.int64), "perm": perm.astype(np.int64)}
 
+    def stable_perm_bytes(self, recs):
+        """Stable ascending permutation of the rows of a uint8 [n, width]
+        array in memcmp order (the paper's string keys, Section 3)."""
+        recs = np.ascontiguousarray(recs, dtype=np.uint8)
+        n, width = recs.shape
+        perm = np.empty(n, dtype=np.uint64)
+        if self.lib.orc_stable_sort_bytes(_ptr(recs), n, width, _ptr(perm)) != 0:
+            raise MemoryError("oracle: out of memory")
+        return perm.astype(np.int64)
+
     def lemma1_bounds(self, n, p, s):
         """Bucket-size bounds of Lemma 1 (Section 2.1) for regular
         oversampling with factor s (the paper's r) and p buckets: with
@@ -180,6 +194,10 @@ class Oracle:
 
 def lemma1_bounds(n, p, s):
     return _get().lemma1_bounds(n, p, s)
+
+
+def stable_perm_bytes(recs):
+    return _get().stable_perm_bytes(recs)
 
 
 _default = None

@@ -371,3 +371,50 @@ void orc_lemma1(uint64_t n, uint32_t p, uint32_t r, uint64_t *out_u, double *out
     out_u[1] = (S + p - 1) * x;
     out_d[0] = (1.0 + 1.0 / (double)r) * (double)n / (double)p + (double)r * (double)p;
 }
+
+/* ------------------------------------------------------ byte-string keys */
+
+/* The paper's measured keys are strings of 32 bytes compared as memcmp
+ * does (Section 3): byte by byte as unsigned values, the first differing
+ * byte deciding.  orc_stable_sort_bytes is the definition of the stable
+ * result for n records of `width` bytes: the unique permutation with
+ * (record, index) strictly increasing, by a top-down merge sort of the
+ * indices that takes the left run on ties. */
+static const uint8_t *g_recs;
+static uint32_t g_width;
+
+static int rec_bytes_less(uint64_t a, uint64_t b)
+{
+    const uint32_t w = (ORC_PLANT == 8 && g_width > 8) ? 8 : g_width;
+    int c = memcmp(g_recs + a * g_width, g_recs + b * g_width, w);
+    return c < 0;
+}
+
+static void merge_sort_idx(uint64_t *a, uint64_t *tmp, uint64_t n)
+{
+    if (n < 2) return;
+    uint64_t h = n / 2;
+    merge_sort_idx(a, tmp, h);
+    merge_sort_idx(a + h, tmp, n - h);
+    uint64_t i = 0, j = h, k = 0;
+    while (i < h && j < n) {
+        /* right before left only if strictly smaller: ties keep input order */
+        if (rec_bytes_less(a[j], a[i])) tmp[k++] = a[j++];
+        else tmp[k++] = a[i++];
+    }
+    while (i < h) tmp[k++] = a[i++];
+    while (j < n) tmp[k++] = a[j++];
+    memcpy(a, tmp, n * sizeof(uint64_t));
+}
+
+int orc_stable_sort_bytes(const uint8_t *recs, uint64_t n, uint32_t width, uint64_t *perm)
+{
+    uint64_t *tmp = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    if (!tmp) return -1;
+    for (uint64_t i = 0; i < n; i++) perm[i] = i;
+    g_recs = recs;
+    g_width = width;
+    merge_sort_idx(perm, tmp, n);
+    free(tmp);
+    return 0;
+}

@@ -17,6 +17,9 @@ distributions of the sort's own workloads:
   [1, 2^20] (log-uniform), with int64 offsets.
 * :func:`tie_free_rows` -- float32 rows drawn from N(0, 1), each row
   redrawn until its values are pairwise distinct.
+* :func:`strings32` -- n records of 32 bytes: uniformly random bytes (the
+  paper's random strings), or records that share 8-, 16- or 24-byte
+  prefixes, or repeat a few whole records (ties at every word).
 """
 import numpy as np
 
@@ -149,3 +152,26 @@ def weak_orderings(n):
         # each ordering of the k blocks gives a distinct weak ordering
         out.append(perms[:, rgs].transpose(1, 0, 2).reshape(-1, n))
     return np.concatenate(out, axis=0)
+
+
+STRING_KINDS = ("random", "prefix", "dup")
+
+
+def strings32(n, seed, kind="random"):
+    """uint8 [n, 32] records.  random: every byte uniform; prefix: a quarter
+    of the records each share their first 8, 16 or 24 bytes with many
+    others (16 distinct prefixes per length); dup: 64 distinct records
+    repeated."""
+    g = rng(seed)
+    recs = g.integers(0, 256, size=(n, 32), dtype=np.uint8)
+    if kind == "prefix":
+        for q, plen in enumerate((8, 16, 24)):
+            rows = np.arange(q, n, 4)
+            pre = g.integers(0, 256, size=(16, plen), dtype=np.uint8)
+            recs[rows, :plen] = pre[g.integers(0, 16, size=rows.size)]
+    elif kind == "dup":
+        base = g.integers(0, 256, size=(64, 32), dtype=np.uint8)
+        recs = base[g.integers(0, 64, size=n)]
+    elif kind != "random":
+        raise ValueError(kind)
+    return np.ascontiguousarray(recs)

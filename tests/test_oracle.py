@@ -247,3 +247,48 @@ def test_p_eff_closed_forms():
     assert oracle.p_eff(1, 2, 1, R) == 1
     # p is rounded down to a power of two
     assert oracle.p_eff(2**20, 100, 4, R) == 64
+
+
+# ------------------------------------------------------------ string keys
+
+def _strings(n, width, alphabet, g, prefix=0):
+    recs = g.integers(0, alphabet, (n, width)).astype(np.uint8)
+    if prefix:
+        recs[:, :prefix] = recs[0, :prefix]          # a common prefix: ties in the leading words
+    return recs
+
+
+def test_bytes_order_matches_python_sorted():
+    """The stable memcmp order equals Python's sort of (bytes, index) tuples
+    (bytes compare as unsigned byte strings), on tiny alphabets with many
+    ties and on full-range bytes."""
+    g = np.random.default_rng(21)
+    for n, width, alphabet in [(1, 4, 2), (6, 3, 2), (50, 5, 3), (400, 32, 256), (300, 9, 2)]:
+        recs = _strings(n, width, alphabet, g)
+        want = sorted(range(n), key=lambda i: (bytes(recs[i]), i))
+        np.testing.assert_array_equal(oracle.stable_perm_bytes(recs), want)
+
+
+def test_bytes_order_brute_force_tiny():
+    """n <= 5: the permutation is the only one whose (record, index) sequence
+    strictly increases, found by trying every permutation."""
+    g = np.random.default_rng(22)
+    for n in range(1, 6):
+        for _ in range(20):
+            recs = _strings(n, 2, 2, g)
+            key = [(bytes(recs[i]), i) for i in range(n)]
+            good = [pm for pm in itertools.permutations(range(n))
+                    if all(key[pm[k]] < key[pm[k + 1]] for k in range(n - 1))]
+            assert len(good) == 1
+            np.testing.assert_array_equal(oracle.stable_perm_bytes(recs), good[0])
+
+
+def test_bytes_order_matches_numpy_lexsort_on_words():
+    """32-byte strings with a shared 16-byte prefix: equal to numpy's stable
+    lexsort on the four big-endian 64-bit words (a library routine that
+    never compares bytes)."""
+    g = np.random.default_rng(23)
+    recs = _strings(20000, 32, 4, g, prefix=16)
+    words = recs.view(">u8").astype(np.uint64)           # [n, 4] big-endian words
+    want = np.lexsort((words[:, 3], words[:, 2], words[:, 1], words[:, 0]))
+    np.testing.assert_array_equal(oracle.stable_perm_bytes(recs), want)

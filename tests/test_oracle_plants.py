@@ -37,6 +37,14 @@ def _lemma1_ok(orc):
     return True
 
 
+def _bytes_ok(orc):
+    g = np.random.default_rng(9)
+    recs = g.integers(0, 3, (500, 32)).astype(np.uint8)
+    recs[:, :10] = 1                                   # shared 10-byte prefix
+    want = sorted(range(500), key=lambda i: (bytes(recs[i]), i))
+    return bool(np.array_equal(orc.stable_perm_bytes(recs), want))
+
+
 CASES = {
     1: ("merge takes the right run on equal keys", _stable_ok),
     2: ("splitter rank off by one", _golden_ok),
@@ -45,11 +53,13 @@ CASES = {
     5: ("tags ignored when keys are equal", _golden_ok),
     6: ("signed keys compared without the sign flip", _stable_ok),
     7: ("Lemma 1 segment length rounded down", _lemma1_ok),
+    8: ("string keys compared on their first 8 bytes only", _bytes_ok),
 }
 
 
 def test_correct_oracle_passes():
-    assert _golden_ok(oracle._get()) and _stable_ok(oracle._get()) and _lemma1_ok(oracle._get())
+    assert _golden_ok(oracle._get()) and _stable_ok(oracle._get()) and _lemma1_ok(oracle._get()) \
+        and _bytes_ok(oracle._get())
 
 
 @pytest.mark.parametrize("plant", sorted(CASES))
