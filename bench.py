@@ -26,7 +26,7 @@ values and (tie-free rows) is therefore the unique sorting permutation;
 the backward routes every gradient through it.
 
 Single workloads (--workload): sort, pairs (2^27 uint64 keys + uint32
-payload), segmented, autograd.
+payload), segmented, autograd, strings (2^25 random 32-byte strings).
 """
 import argparse
 import ctypes
@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sort", choices=["sort", "pairs", "segmented", "autograd"])
+    ap.add_argument("--workload", default="sort", choices=["sort", "pairs", "segmented", "autograd", "strings"])
     ap.add_argument("--log2n", type=int, default=26)
     ap.add_argument("--p", type=int, default=4096)
     ap.add_argument("--s", type=int, default=16)
@@ -519,6 +519,43 @@ def bench_autograd(steps, warmup):
     return res, ok
 
 
+def bench_strings(args):
+    """2^25 random 32-byte strings (1 GiB, the paper's workload shape):
+    stable memcmp-order sort through the index, permutation and sorted
+    strings; checked without the oracle (the sorted strings do not decrease
+    as big-endian words, and the permutation is one)."""
+    import numpy as np
+    import torch
+
+    from paper_1608_08648_amd import api, workloads
+
+    n = 1 << (args.log2n if args.log2n != 26 else 25)
+    seed = workloads.seed_for(7, 0)
+    recs = workloads.strings32(n, seed, "random")
+    rd = torch.from_numpy(recs).cuda()
+    out = torch.empty_like(rd)
+    ws = api._workspace(api.strings_workspace_size(n, 32, None), rd.device)
+
+    def step():
+        api.sort_strings(rd, recs_out=out, ws=ws)
+
+    ms = _timed(step, args.steps, args.warmup)
+    perm, _ = api.sort_strings(rd, recs_out=out, ws=ws)
+    w = out.view(torch.int64).view(n, 4).cpu().numpy().view(np.uint64).byteswap()
+    srt = np.lexsort((w[:, 3], w[:, 2], w[:, 1], w[:, 0]))
+    ok = bool(np.array_equal(srt, np.arange(n)))
+    pp = perm.cpu().numpy()
+    ok = ok and bool(np.array_equal(np.sort(pp), np.arange(n))) and bool(np.array_equal(recs[pp], out.cpu().numpy()))
+    gs = n / (ms / 1e3) / 1e9
+    return {"metric": "Gstrings/s, stable sample sort of 2^25 random 32-byte strings (memcmp order)",
+            "value": round(gs, 4), "unit": "Gstrings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u8x32", "data": "synthetic",
+            "config": {"workload": f"{n} random 32-byte strings, permutation and sorted strings", "n": n,
+                       "params": "tuned (prm = NULL)", "seed": seed},
+            "check": "sorted strings non-decreasing, a permutation, recs[perm] == sorted" if ok else "FAILED"}, ok
+
+
 def _single_line(name, res, args):
     d = {"metric": {"segmented": "Gkeys/s, batched segmented sample sort (one graph) vs one call per segment",
                     "autograd": "Gelem/s, differentiable row sort forward of 64 x 2^18 float32"}[name],
@@ -558,6 +595,8 @@ def main():
             ok = ok and ok1 and ok2
     elif args.workload == "pairs":
         res, ok = bench_pairs(args)
+    elif args.workload == "strings":
+        res, ok = bench_strings(args)
     elif args.workload == "segmented":
         seg, ok = bench_segmented(args.steps, args.warmup)
         res = _single_line("segmented", seg, args)

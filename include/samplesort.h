@@ -173,6 +173,25 @@ int sample_sort_keys_noalloc(const void *keys_in, void *keys_out, size_t n, int 
 /* Bytes of the static scratch array of sample_sort_keys_noalloc.  Host only. */
 size_t ss_noalloc_capacity_bytes(void);
 
+/* Fixed-width byte strings (the paper's measured keys, Section 3: random
+ * 32-byte strings compared as memcmp does), sorted stably through their
+ * index.  recs: device array of n strings of `width` bytes (a multiple of
+ * 8 in [8, 256]), 8-byte aligned; perm_out: device int64[n], the stable
+ * sorting permutation (string perm_out[i] is the i-th smallest, equal
+ * strings in input order); recs_out: NULL, or a device array of n * width
+ * bytes (8-byte aligned, not overlapping recs) that receives the sorted
+ * strings.  The strings are not moved during the sort: their 64-bit
+ * prefix words, read big-endian, travel with the index -- word 0 through
+ * the pairs sort (sample, splitters, classification and buckets compare
+ * the word), then, for runs of strings whose words so far are all equal,
+ * the next word through the segmented sort, until no such run is left.
+ * The call waits for `stream` once per round after the first (it reads
+ * how many strings are still tied), so it cannot be captured into a HIP
+ * graph.  prm: as for sample_sort_pairs (NULL = tuned). */
+int ss_strings_workspace_size(size_t n, uint32_t width, const ss_params *prm, size_t *bytes_out);
+int sample_sort_strings(const void *recs, void *recs_out, int64_t *perm_out, size_t n, uint32_t width,
+                        const ss_params *prm, void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace bytes for segmented_sort: `total` keys in `num_segments`
  * segments, none longer than `max_seg_len` (0 = unknown, taken as total). */
 int ss_segmented_workspace_size(size_t total, size_t num_segments, size_t max_seg_len, int key_type,

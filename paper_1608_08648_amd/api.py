@@ -227,6 +227,33 @@ def scatter_grad(grad_y, perm, grad_x=None, stream=None):
     return grad_x
 
 
+def strings_workspace_size(n, width, prm=None):
+    out = ctypes.c_size_t()
+    N.check(N.lib().ss_strings_workspace_size(n, width, _pref(prm), ctypes.byref(out)))
+    return out.value
+
+
+def sort_strings(recs, prm=None, recs_out=None, want_sorted=True, ws=None, stream=None):
+    """Stable memcmp-order sort of fixed-width byte strings: recs is a uint8
+    device tensor [n, width] (width a multiple of 8).  Returns (perm int64
+    [n], sorted strings [n, width] or None)."""
+    _check_dev(recs)
+    if recs.dtype != torch.uint8 or recs.dim() != 2:
+        raise ValueError("recs must be a 2-D uint8 tensor [n, width]")
+    n, width = recs.shape
+    perm = torch.empty(n, dtype=torch.int64, device=recs.device)
+    if want_sorted and recs_out is None:
+        recs_out = torch.empty_like(recs)
+    if recs_out is not None:
+        _check_dev(recs_out)
+        if recs_out.shape != recs.shape or recs_out.dtype != torch.uint8 or recs_out.device != recs.device:
+            raise ValueError("recs_out must match recs")
+    w = _workspace(strings_workspace_size(n, width, prm), recs.device, ws)
+    N.check(N.lib().sample_sort_strings(_ptr(recs), _ptr(recs_out), _ptr(perm), n, width, _pref(prm), _ptr(w),
+                                        w.numel(), _stream(stream)))
+    return perm, recs_out
+
+
 def grad_status(stream=None):
     """Wait for the stream; raise if a scatter_grad call since the last check
     met a permutation index outside its row."""

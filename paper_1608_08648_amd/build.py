@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libsamplesort.so")
 SOURCES = [os.path.join(CSRC, "samplesort.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("ss_kernels.h", "ss_device.h", "ss_wide.h", "ss_pairs.h", "ss_sortfirst.h", "ss_tuned.h")] + [
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("ss_kernels.h", "ss_device.h", "ss_wide.h", "ss_pairs.h", "ss_sortfirst.h", "ss_tuned.h", "ss_strings.h")] + [
     os.path.join(os.path.dirname(HERE), "include", "samplesort.h")]
 
 

@@ -8,6 +8,7 @@
 #include "ss_pairs.h"
 #include "ss_sortfirst.h"
 #include "ss_tuned.h"
+#include "ss_strings.h"
 
 #include <hip/hip_runtime.h>
 
@@ -1092,6 +1093,151 @@ int sort_common(const void* keys_in, const void* vals_in, void* keys_out, void* 
   return run_single_any(P, (char*)ws, keys_in, vals_in, keys_out, vals_out, as_stream(stream));
 }
 
+// ------------------------------------------------------- string keys
+//
+// Layout and plans of a string sort: the prefix words, the index, the
+// round-0 pairs sort, the run flags and their scans, the gathered runs and
+// the segmented sort that orders them.
+struct StrPlan {
+  uint64_t n = 0;
+  uint32_t width = 0, W = 0;
+  Plan pairs;            // round 0: (word 0, index) pairs
+  Plan seg;              // later rounds: the runs as segments, planned for the largest case
+  size_t o_w = 0, o_w2 = 0, o_perm = 0, o_b = 0, o_f = 0, o_g = 0, o_fp = 0, o_gp = 0;
+  size_t o_kt = 0, o_vt = 0, o_pt = 0, o_ks = 0, o_vs = 0, o_off = 0, o_pairs = 0, o_seg = 0;
+  size_t bytes = 0;
+};
+
+int plan_strings(StrPlan* S, uint64_t n, uint32_t width, const ss_params* prm) {
+  if (width < 8 || width > 256 || width % 8) return fail(SS_EINVAL, "width = %u: a multiple of 8 in [8, 256]", width);
+  if (n >= (1ull << 32) - 1) return fail(SS_EINVAL, "n = %llu: fewer than 2^32 - 1 strings", (unsigned long long)n);
+  S->n = n;
+  S->width = width;
+  S->W = width / 8;
+  Types kt, st;
+  parse_types(SS_U64, SS_V_IOTA32, &kt);
+  parse_types(SS_U64, SS_V_B32, &st);
+  ss_params p0, p1;
+  int rc = check_params(prm, &p0, kt, n);
+  if (rc) return rc;
+  rc = check_params(prm, &p1, st, n, 1);
+  if (rc) return rc;
+  rc = plan_single(&S->pairs, n, kt, p0);
+  if (rc) return rc;
+  const uint64_t nseg = std::max<uint64_t>(n / 2, 1);
+  rc = plan_segmented(&S->seg, n, nseg, n, st, p1, prm != nullptr);
+  if (rc) return rc;
+  Layout L;
+  const uint64_t m = std::max<uint64_t>(n, 1);
+  S->o_w = L.take(8 * m);
+  S->o_w2 = L.take(8 * m);
+  S->o_perm = L.take(4 * m);
+  S->o_b = L.take(m);
+  S->o_f = L.take(4 * (m + 1));
+  S->o_g = L.take(4 * (m + 1));
+  S->o_fp = L.take(4 * (cdiv(m + 1, SCAN_BLOCK) + 1));
+  S->o_gp = L.take(4 * (cdiv(m + 1, SCAN_BLOCK) + 1));
+  S->o_kt = L.take(8 * m);
+  S->o_vt = L.take(4 * m);
+  S->o_pt = L.take(4 * m);
+  S->o_ks = L.take(8 * m);
+  S->o_vs = L.take(4 * m);
+  S->o_off = L.take(8 * (nseg + 1));
+  S->o_pairs = L.take(S->pairs.bytes);
+  S->o_seg = L.take(S->seg.bytes);
+  S->bytes = L.cur;
+  return SS_OK;
+}
+
+int sort_strings(const void* recs, void* recs_out, int64_t* perm_out, size_t n, uint32_t width, const ss_params* prm,
+                 void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  StrPlan S;
+  int rc = plan_strings(&S, n, width, prm);
+  if (rc) return rc;
+  if (n == 0) return SS_OK;
+  if (!recs || !perm_out) return fail(SS_EINVAL, "recs and perm_out must be device pointers");
+  if (((uintptr_t)recs | (uintptr_t)recs_out) % 8) return fail(SS_EINVAL, "recs and recs_out must be 8-byte aligned");
+  if (overlap_partial(recs, (size_t)n * width, recs_out, (size_t)n * width) || recs == recs_out)
+    return fail(SS_EINVAL, "recs_out must not overlap recs");
+  if (!ws || ws_bytes < S.bytes || ((uintptr_t)ws) % ALIGN)
+    return fail(SS_EWORKSPACE, "workspace of %zu bytes (aligned to %zu) needed", S.bytes, ALIGN);
+  hipStream_t st = as_stream(stream);
+  char* b = (char*)ws;
+  const uint8_t* R = (const uint8_t*)recs;
+  uint64_t* w = (uint64_t*)(b + S.o_w);
+  uint64_t* w2 = (uint64_t*)(b + S.o_w2);
+  uint32_t* perm = (uint32_t*)(b + S.o_perm);
+  uint8_t* bd = (uint8_t*)(b + S.o_b);
+  uint32_t* f = (uint32_t*)(b + S.o_f);
+  uint32_t* g = (uint32_t*)(b + S.o_g);
+  const uint32_t grid = grid_of(n, 256, 8192);
+  // round 0: word 0 with the index, stable pairs sort
+  LAUNCH(PK_SAMPLE, k_str_word, dim3(grid), dim3(256), 0, st, R, width, 0u, (const uint32_t*)nullptr, w, (uint64_t)n);
+  LAUNCH_CHECK();
+  rc = run_single_any(S.pairs, b + S.o_pairs, w, nullptr, w2, perm, st);
+  if (rc) return rc;
+  uint64_t* cur = w2;
+  for (uint32_t k = 1; k < S.W; k++) {
+    LAUNCH(PK_CLASSIFY, k_str_flags, dim3(grid_of(n + 1, 256, 8192)), dim3(256), 0, st, (const uint64_t*)cur,
+           k == 1 ? (const uint8_t*)nullptr : (const uint8_t*)bd, bd, f, g, (uint64_t)n);
+    LAUNCH_CHECK();
+    const uint64_t tot1 = n + 1;
+    const uint32_t nb = (uint32_t)cdiv(tot1, SCAN_BLOCK);
+    ScanPair q;
+    q.h2 = g;
+    q.part2 = (uint32_t*)(b + S.o_gp);
+    q.total2 = tot1;
+    q.nb1 = nb;
+    uint32_t* fp = (uint32_t*)(b + S.o_fp);
+    LAUNCH(PK_SCAN, k_scan_reduce, dim3(2 * nb), dim3(NT), 0, st, f, fp, tot1, (const uint64_t*)nullptr, q);
+    LAUNCH(PK_SCAN, k_scan_partials, dim3(2), dim3(NT), 0, st, fp, tot1, (const uint64_t*)nullptr, q);
+    LAUNCH(PK_SCAN, k_scan_down, dim3(2 * nb), dim3(NT), 0, st, f, fp, tot1, (const uint64_t*)nullptr, q);
+    LAUNCH_CHECK();
+    // how many strings sit in runs of equal prefixes, in how many runs
+    uint32_t tot = 0, nruns = 0;
+    HIP_TRY(hipMemcpyAsync(&tot, f + n, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&nruns, g + n, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (tot == 0) break;
+    uint64_t* kt = (uint64_t*)(b + S.o_kt);
+    uint32_t* vt = (uint32_t*)(b + S.o_vt);
+    uint32_t* pt = (uint32_t*)(b + S.o_pt);
+    uint64_t* ks = (uint64_t*)(b + S.o_ks);
+    uint32_t* vs = (uint32_t*)(b + S.o_vs);
+    int64_t* off = (int64_t*)(b + S.o_off);
+    LAUNCH(PK_SCATTER, k_str_gather, dim3(grid_of(n + 1, 256, 8192)), dim3(256), 0, st, R, width, k,
+           (const uint8_t*)bd, (const uint32_t*)f, (const uint32_t*)g, (const uint32_t*)perm, kt, vt, pt, off,
+           (uint64_t)n);
+    LAUNCH_CHECK();
+    // the runs as segments (planned for this round's sizes, inside the
+    // workspace planned for the largest case)
+    Types sty;
+    parse_types(SS_U64, SS_V_B32, &sty);
+    ss_params p1;
+    rc = check_params(prm, &p1, sty, tot, 1);
+    if (rc) return rc;
+    Plan P;
+    rc = plan_segmented(&P, tot, nruns, tot, sty, p1, prm != nullptr);
+    if (rc) return rc;
+    if (P.bytes > S.seg.bytes) return fail(SS_EWORKSPACE, "string round plan exceeds its workspace");
+    rc = run_segmented_any(P, b + S.o_seg, kt, vt, ks, vs, off, st);
+    if (rc) return rc;
+    LAUNCH(PK_SCATTER, k_str_scatter, dim3(grid_of(tot, 256, 8192)), dim3(256), 0, st, (const uint64_t*)ks,
+           (const uint32_t*)vs, (const uint32_t*)pt, perm, cur, (const uint32_t*)f, (uint64_t)n);
+    LAUNCH_CHECK();
+  }
+  LAUNCH(PK_WIDEN, k_widen_index, dim3(grid), dim3(256), 0, st, (const uint32_t*)perm, perm_out,
+         (const int64_t*)nullptr, (uint64_t)0, (uint64_t)n);
+  LAUNCH_CHECK();
+  if (recs_out) {
+    LAUNCH(PK_SCATTER, k_str_permute, dim3(grid_of((uint64_t)n * (width / 8), 256, 8192)), dim3(256), 0, st, R,
+           (uint8_t*)recs_out, (const uint32_t*)perm, width, (uint64_t)n);
+    LAUNCH_CHECK();
+  }
+  return SS_OK;
+}
+
 // -------------------------------------------------- no-allocation entry
 //
 // sample_sort_keys_noalloc runs the keys-only sort with its workspace in a
@@ -1154,6 +1300,21 @@ int sample_sort_keys_noalloc(const void* keys_in, void* keys_out, size_t n, int 
 }
 
 size_t ss_noalloc_capacity_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
+
+int ss_strings_workspace_size(size_t n, uint32_t width, const ss_params* prm, size_t* bytes_out) {
+  g_err[0] = 0;
+  if (!bytes_out) return fail(SS_EINVAL, "bytes_out is NULL");
+  StrPlan S;
+  int rc = plan_strings(&S, n, width, prm);
+  if (rc) return rc;
+  *bytes_out = S.bytes;
+  return SS_OK;
+}
+
+int sample_sort_strings(const void* recs, void* recs_out, int64_t* perm_out, size_t n, uint32_t width,
+                        const ss_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  return sort_strings(recs, recs_out, perm_out, n, width, prm, ws, ws_bytes, stream);
+}
 
 const char* ss_last_error(void) { return g_err; }
 

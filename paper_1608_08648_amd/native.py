@@ -30,7 +30,7 @@ SS_MAX_LEVELS = 6
 EXPORTS = ("ss_last_error", "ss_workspace_size", "ss_stage_layout", "sample_sort_keys", "sample_sort_pairs",
            "ss_segmented_workspace_size", "segmented_sort", "ss_scatter_grad", "ss_status", "ss_level_stats",
            "ss_set_tuning", "ss_get_tuning", "ss_grad_status", "sample_sort_keys_noalloc",
-           "ss_noalloc_capacity_bytes",
+           "ss_noalloc_capacity_bytes", "ss_strings_workspace_size", "sample_sort_strings",
            "ss_profile_enable", "ss_profile_kinds", "ss_profile_collect", "ss_profile_report")
 
 
@@ -90,6 +90,8 @@ def lib():
         L.ss_grad_status.argtypes = [P]
         L.sample_sort_keys_noalloc.argtypes = [P, P, SZ, I, PP, P]
         L.ss_noalloc_capacity_bytes.argtypes = []
+        L.ss_strings_workspace_size.argtypes = [SZ, ctypes.c_uint32, PP, ctypes.POINTER(SZ)]
+        L.sample_sort_strings.argtypes = [P, P, P, SZ, ctypes.c_uint32, PP, P, SZ, P]
         L.ss_level_stats.argtypes = [P, I, ctypes.POINTER(LevelInfo), P]
         L.ss_set_tuning.argtypes = [ctypes.POINTER(TuneEntry), SZ]
         L.ss_get_tuning.argtypes = [I, I, I, SZ, PP]

@@ -227,3 +227,18 @@ def test_tuning_table_set_get_restore():
     finally:
         assert L.ss_set_tuning(None, 0) == 0
     assert _tuned(0, N.SS_I32, N.SS_V_NONE, 2**20) != (512, 8, 65536)
+
+
+def test_strings_workspace_and_refusals():
+    L = N.lib()
+    out = ctypes.c_size_t()
+    assert L.ss_strings_workspace_size(1 << 20, 32, None, ctypes.byref(out)) == 0
+    assert out.value >= (1 << 20) * 32                   # words, index, runs and the sorts' workspaces
+    for w in (0, 7, 12, 264):
+        assert L.ss_strings_workspace_size(1000, w, None, ctypes.byref(out)) == N.SS_EINVAL
+    P = ctypes.c_void_p
+    # unaligned strings, or no permutation output: refused before any launch
+    assert L.sample_sort_strings(P(4097), None, P(8192), 10, 32, None, P(1 << 20), 1 << 30, None) == N.SS_EINVAL
+    assert L.sample_sort_strings(P(4096), None, None, 10, 32, None, P(1 << 20), 1 << 30, None) == N.SS_EINVAL
+    assert L.sample_sort_strings(P(4096), P(4096), P(8192), 10, 32, None, P(1 << 20), 1 << 30, None) == N.SS_EINVAL
+    assert L.sample_sort_strings(P(4096), None, P(8192), 10, 32, None, None, 0, None) == N.SS_EWORKSPACE
