@@ -48,8 +48,8 @@ HBM_PEAK_GBS = 8000.0
 # on; "traffic" is null for anything else.
 MEASURED_TRAFFIC = {
     ("bucket_sort", 26, 4096, 16, "random", "uniform"): {
-        "src_sha256_16": "aa688b34526e6d20",
-        "bytes_per_launch": 829896301,   # k_wide_bucket<16000, 13>: FETCH 273,650 KiB x 2 + WRITE 263,146 KiB
+        "src_sha256_16": "a8dd4a0d909c3496",
+        "bytes_per_launch": 830784512,   # k_wide_bucket<16000, 13>: FETCH 274,083 KiB x 2 + WRITE 263,147 KiB
     },
 }
 
