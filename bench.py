@@ -26,7 +26,8 @@ values and (tie-free rows) is therefore the unique sorting permutation;
 the backward routes every gradient through it.
 
 Single workloads (--workload): sort, pairs (2^27 uint64 keys + uint32
-payload), segmented, autograd, strings (2^25 random 32-byte strings).
+payload), segmented, autograd, strings (2^25 random 32-byte strings),
+regular (2^20 uint32, regular oversampling p = 64, s = 8).
 """
 import argparse
 import ctypes
@@ -59,7 +60,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sort", choices=["sort", "pairs", "segmented", "autograd", "strings"])
+    ap.add_argument("--workload", default="sort",
+                    choices=["sort", "pairs", "segmented", "autograd", "strings", "regular"])
     ap.add_argument("--log2n", type=int, default=26)
     ap.add_argument("--p", type=int, default=4096)
     ap.add_argument("--s", type=int, default=16)
@@ -556,6 +558,48 @@ def bench_strings(args):
             "check": "sorted strings non-decreasing, a permutation, recs[perm] == sorted" if ok else "FAILED"}, ok
 
 
+def bench_regular(args):
+    """2^20 uint32 keys uniform on [0, 2^32), regular oversampling (Alg. 1)
+    with p = 64, s (the paper's r) = 8: the small configuration.  Checked
+    without the oracle: sorted, same multiset, and the largest bucket
+    within Lemma 1's bound (S + p - 1) * x, S = s p, x = ceil(ceil(n/p)/S)."""
+    import numpy as np
+    import torch
+
+    from paper_1608_08648_amd import api, native as N, workloads
+
+    n, p, s = 1 << 20, 64, 8
+    seed = workloads.seed_for(0)
+    keys = workloads.uniform_u32(n, seed)
+    kd = torch.from_numpy(keys.view(np.int32)).cuda()
+    out = torch.empty_like(kd)
+    prm = api.params(p=p, s=s, sampling="regular", seed=1234)
+    ws = api._workspace(api.workspace_size(n, N.SS_U32, N.SS_V_NONE, prm), kd.device)
+
+    def step():
+        api.sort_keys(kd, prm, out=out, ws=ws, key_type="u32")
+
+    ms = _timed(step, args.steps, args.warmup)
+    kernels = _kernel_table(step, max(1, min(args.steps, 5)))
+    o, st, info = api.stages(kd, prm, key_type="u32")
+    got = o.cpu().numpy().view(np.uint32)
+    ok = bool(np.all(got[1:] >= got[:-1])) and fingerprint(got) == fingerprint(keys)
+    S = s * p
+    x = -(-(-(-n // p)) // S)
+    bound = (S + p - 1) * x
+    mx = int(st["counts"].max())
+    ok = ok and mx <= bound
+    gk = n / (ms / 1e3) / 1e9
+    return {"metric": "Gkeys/s, sample sort of 2^20 uint32 keys, regular oversampling p = 64, s = 8",
+            "value": round(gk, 4), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "2^20 uint32 uniform, keys only, regular oversampling (Alg. 1)", "n": n, "p": p,
+                       "s": s, "sample": int(info.m), "seed": seed},
+            "largest_bucket": mx, "lemma1_bound": bound, "mean_bucket": n // p, "kernels": kernels,
+            "check": "sorted+multiset, largest bucket within Lemma 1" if ok else "FAILED"}, ok
+
+
 def _single_line(name, res, args):
     d = {"metric": {"segmented": "Gkeys/s, batched segmented sample sort (one graph) vs one call per segment",
                     "autograd": "Gelem/s, differentiable row sort forward of 64 x 2^18 float32"}[name],
@@ -597,6 +641,8 @@ def main():
         res, ok = bench_pairs(args)
     elif args.workload == "strings":
         res, ok = bench_strings(args)
+    elif args.workload == "regular":
+        res, ok = bench_regular(args)
     elif args.workload == "segmented":
         seg, ok = bench_segmented(args.steps, args.warmup)
         res = _single_line("segmented", seg, args)
