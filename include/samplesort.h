@@ -66,13 +66,15 @@ enum { SS_RANDOM = 0,   /* Alg. 2: p*s-1 keys drawn uniformly (with replacement)
 #define SS_F_SORT_FIRST    16u  /* the organisation Alg. 1 and Alg. 2 state: sort the p blocks
                                    first (step 1), place the splitters in each sorted block by
                                    binary search (step 4), and form bucket j from the p runs the
-                                   splitters cut out of the blocks (step 5).  4-byte keys without
-                                   payload only (SS_EINVAL otherwise); no level below.  Without
-                                   the flag the keys are classified and moved unsorted (the
-                                   split-first organisation, the default). */
+                                   splitters cut out of the blocks (step 5).  Every key type and
+                                   payload; single arrays only (SS_EINVAL for the segmented
+                                   sort); p at most SS_P_MAX; no level below.  Without the flag
+                                   the keys are classified and moved unsorted (the split-first
+                                   organisation, the default). */
 #define SS_F_SF_MERGE      32u  /* with SS_F_SORT_FIRST: step 5 merges each bucket's p runs (the
                                    paper's merging, lg p pairwise rounds in LDS) instead of
-                                   gathering them and sorting the bucket */
+                                   gathering them and sorting the bucket.  4-byte keys without
+                                   payload only (SS_EINVAL otherwise). */
 
 /* return codes */
 enum { SS_OK = 0, SS_EINVAL = -1, SS_EWORKSPACE = -2, SS_EHIP = -3, SS_EDEVICE = -4 };

@@ -384,6 +384,9 @@ struct Plan {
   // sort-first organisation: sorted blocks (o_regk, o_regi), the run table and the buckets
   bool sortfirst = false;
   size_t o_sfpos = 0, o_sfbkt = 0;
+  // sort-first with 8-byte keys or a payload: the gathered buckets, sorted as segments
+  Plan* nested_b = nullptr;
+  size_t o_sfoff = 0, o_nested_b = 0;
   // a large sample of 4-byte keys: packed records and the nested sort that orders them
   Plan* nested_s = nullptr;
   size_t o_spack = 0, o_nested_s = 0;
@@ -397,6 +400,7 @@ struct Plan {
   ~Plan() {
     delete nested;
     delete nested_s;
+    delete nested_b;
   }
 };
 
@@ -430,8 +434,8 @@ int plan_single_t(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   P->n = n;
   P->prm = prm;
   if (n >= (1ull << 32)) return fail(SS_EINVAL, "n = %llu: at most 2^32-1 keys per array", (unsigned long long)n);
-  if ((prm.flags & SS_F_SORT_FIRST) && !(ty.KW == 4 && ty.VW == 0))
-    return fail(SS_EINVAL, "SS_F_SORT_FIRST: 4-byte keys without payload only");
+  if ((prm.flags & SS_F_SF_MERGE) && (prm.flags & SS_F_SORT_FIRST) && !(ty.KW == 4 && ty.VW == 0))
+    return fail(SS_EINVAL, "SS_F_SF_MERGE: 4-byte keys without payload only");
   const uint32_t C = small_cap(ty.KW, ty.VW);
   Layout L;
   P->o_ctl = L.take(sizeof(Ctl));
@@ -522,6 +526,22 @@ int plan_single_t(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
   if (P->sortfirst) {
     P->o_sfpos = L.take(4 * (size_t)p * (p + 1));
     P->o_sfbkt = L.take(8 * (size_t)p);
+    if (!(ty.KW == 4 && ty.VW == 0)) {
+      // step 5 gathers each bucket's runs with their payloads (an index
+      // payload becomes a stored one), then sorts the p buckets as segments
+      // of any length up to n
+      Types gt = ty;
+      gt.iota = false;
+      gt.vt = ty.VW == 0 ? SS_V_NONE : (ty.VW == 4 ? SS_V_B32 : SS_V_B64);
+      ss_params gp = prm;
+      gp.sampling = SS_RANDOM;
+      gp.flags &= SS_F_NO_RECURSION;
+      P->nested_b = new Plan();
+      int rc = plan_segmented(P->nested_b, n, p, n, gt, gp, false);
+      if (rc) return rc;
+      P->o_sfoff = L.take(8 * ((size_t)p + 1));
+      P->o_nested_b = L.take(P->nested_b->bytes);
+    }
   }
   if (P->regular || P->sortfirst) {
     // blocks sorted with their in-block index as payload (Alg. 1 step 1)
@@ -802,8 +822,8 @@ int run_sort_first(const Plan& P, char* ws, LevelArgs a, void* out, int exp, hip
   f.lgp = 31 - __builtin_clz(P.p_eff);
   f.kind = P.ty.kind;
   const uint64_t bmax = cdiv(P.n, f.p);   // longest block
-  f.lds_keys = bmax <= SF_LDS_KEYS ? (uint32_t)bmax : 0u;
-  LAUNCH(PK_SF_SEARCH, k_sf_search, dim3(f.p), dim3(SF_NT), 4 * (size_t)f.lds_keys, st, f);
+  f.lds_keys = bmax <= SF_LDS_BYTES / 4 ? (uint32_t)bmax : 0u;
+  LAUNCH(PK_SF_SEARCH, k_sf_search<4>, dim3(f.p), dim3(SF_NT), 4 * (size_t)f.lds_keys, st, f);
   LAUNCH_CHECK();
   a.dst = f.stage;
   a.out = out;
@@ -822,6 +842,43 @@ int run_sort_first(const Plan& P, char* ws, LevelArgs a, void* out, int exp, hip
   LAUNCH(PK_BUCKET_LEFT, (k_bucket_leftover_keys<4>), dim3(std::min<uint32_t>(f.p, 512)), dim3(NT), 0, st, a, 0);
   LAUNCH_CHECK();
   return SS_OK;
+}
+
+template <int KW, int VW>
+int run_segmented(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout,
+                  const int64_t* off, hipStream_t st);
+
+// Sort-first organisation for 8-byte keys or with a payload: step 4 as
+// above; step 5 gathers bucket j's runs (with the payload of each key) into
+// the stage and sorts the p buckets as segments into the output.
+template <int KW, int VW>
+int run_sort_first_any(const Plan& P, char* ws, LevelArgs a, const void* vin, void* out, void* vout, int exp,
+                       hipStream_t st) {
+  SfArgs f{};
+  f.bkeys = (const uint32_t*)(ws + P.o_regk);
+  f.bidx = (const uint32_t*)(ws + P.o_regi);
+  f.tree = (const uint64_t*)a.tree;
+  f.tree_tag = a.tree_tag;
+  f.pos = (uint32_t*)(ws + P.o_sfpos);
+  f.bkt = (uint2*)(ws + P.o_sfbkt);
+  f.n = P.n;
+  f.p = P.p_eff;
+  f.lgp = 31 - __builtin_clz(P.p_eff);
+  f.kind = P.ty.kind;
+  const uint64_t bmax = cdiv(P.n, f.p);
+  f.lds_keys = bmax <= SF_LDS_BYTES / KW ? (uint32_t)bmax : 0u;
+  LAUNCH(PK_SF_SEARCH, k_sf_search<KW>, dim3(f.p), dim3(SF_NT), (size_t)KW * f.lds_keys, st, f);
+  LAUNCH_CHECK();
+  void* kst = ws + P.o_tmp;
+  void* vst = VW ? (void*)(ws + P.o_vtmp) : nullptr;
+  int64_t* off = (int64_t*)(ws + P.o_sfoff);
+  LAUNCH(PK_SF_GATHER, (k_sf_gather_any<KW, VW>), dim3(f.p), dim3(SF_GNT), 0, st, f, kst, vst, vin,
+         P.ty.iota ? 1 : 0, off, exp ? a.exp_counts : nullptr);
+  LAUNCH_CHECK();
+  g_prof_force = PK_BUCKET_SORT;
+  const int rc = run_segmented<KW, VW>(*P.nested_b, ws + P.o_nested_b, kst, vst, out, vout, off, st);
+  g_prof_force = -1;
+  return rc;
 }
 
 template <int KW, int VW>
@@ -877,8 +934,11 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       LAUNCH(PK_SAMPLE_SORT, k_sample_sort_wg<KW>, dim3(lv.seg_cap), dim3(NT), 0, st, a, exp);
     }
     LAUNCH_CHECK();
+    if (l == 0 && P.sortfirst) {
+      if constexpr (KW == 4 && VW == 0) return run_sort_first(P, ws, a, out, exp, st);
+      else return run_sort_first_any<KW, VW>(P, ws, a, vin, out, vout, exp, st);
+    }
     if constexpr (KW == 4 && VW == 0) {
-      if (l == 0 && P.sortfirst) return run_sort_first(P, ws, a, out, exp, st);
       if (l == 0 && P.wide) {
         int rc = run_wide(P, ws, a, in, out, exp, st);
         if (rc) return rc;

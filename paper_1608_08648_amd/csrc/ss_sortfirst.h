@@ -1,5 +1,4 @@
-// Sort-first organisation of the method, as Alg. 1 and Alg. 2 state it, for
-// 4-byte keys without payload:
+// Sort-first organisation of the method, as Alg. 1 and Alg. 2 state it:
 //   step 1  the p blocks [floor(k n / p), floor((k+1) n / p)) are sorted by
 //           (key, in-block index) (the segmented path, index as payload);
 //   steps 2-3 the sample (regular: from the sorted blocks, Alg. 1; random:
@@ -12,7 +11,10 @@
 //           pairwise (k_sf_merge, SS_F_SF_MERGE: the merging the paper
 //           states), or gathered in block order and sorted in LDS with the
 //           round-based slot sort (the default); the concatenation of the
-//           buckets is the output.
+//           buckets is the output.  Those two forms of step 5 take 4-byte
+//           keys without payload; 8-byte keys and every payload are gathered
+//           with their payloads (k_sf_gather_any) and the p buckets sorted
+//           as segments by the segmented path.
 // Keys compare as (ord(key), global index), the same total order as the
 // split-first classification, so bucket j holds exactly the keys that
 // classification puts in bucket j.
@@ -22,14 +24,16 @@
 namespace ss {
 
 constexpr int SF_NT = 1024;                // threads of the search kernel
-constexpr uint32_t SF_LDS_KEYS = 16384;    // sorted block keys the search holds in LDS (at most 64 KB)
+constexpr uint32_t SF_LDS_BYTES = 65536;   // sorted block keys the search holds in LDS (at most 64 KB)
 constexpr uint32_t SF_PMAX = 4096;         // largest p: the gather kernel's run table (32 KB)
 constexpr int SF_GNT = 512;                // threads of the gather kernel
 
 struct SfArgs {
-  const uint32_t* bkeys;   // step 1: the sorted blocks (keys as given)
+  const uint32_t* bkeys;   // step 1: the sorted blocks (keys as given; 8-byte keys: two words each)
   const uint32_t* bidx;    // in-block index of each sorted key
-  const uint64_t* tree;    // Eytzinger tree of the splitters, slot k in [1, p): (ord << 32) | tag
+  const uint64_t* tree;    // Eytzinger tree of the splitters, slot k in [1, p): (ord << 32) | tag for
+                           // 4-byte keys; the ord for 8-byte keys, whose tags are in tree_tag
+  const uint32_t* tree_tag;
   uint32_t* pos;           // p rows of p + 1: pos[k (p+1) + j] = start of X_{k,j} in sorted block k
   uint2* bkt;              // per bucket: (output start, size)
   uint32_t* stage;         // step 5: the gathered buckets, as ord keys
@@ -54,15 +58,19 @@ __device__ __forceinline__ uint64_t sf_splitter(const uint64_t* tree, uint32_t l
 // belongs to the bucket of the first splitter not below it, so a sampled
 // key equal to splitter j stays in bucket j - 1, as the classification
 // #{splitters < (key, index)} has it).
+template <int KW>
 __global__ void __launch_bounds__(SF_NT) k_sf_search(SfArgs f) {
-  extern __shared__ uint32_t sk[];   // f.lds_keys keys
+  using KT = typename KeyOf<KW>::T;
+  extern __shared__ uint64_t sk_raw[];   // f.lds_keys keys
+  KT* sk = (KT*)sk_raw;
+  const KT* bkeys = (const KT*)f.bkeys;
   const uint32_t k = blockIdx.x;
   if (k >= f.p) return;
   const uint64_t bs = sf_block_start(f.n, f.p, k);
   const uint32_t len = (uint32_t)(sf_block_start(f.n, f.p, k + 1) - bs);
   const bool lds = len <= f.lds_keys;
   if (lds)
-    for (uint32_t i = threadIdx.x; i < len; i += SF_NT) sk[i] = to_ord(f.bkeys[bs + i], f.kind);
+    for (uint32_t i = threadIdx.x; i < len; i += SF_NT) sk[i] = to_ord(bkeys[bs + i], f.kind);
   __syncthreads();
   uint32_t* row = f.pos + (uint64_t)k * (f.p + 1);
   for (uint32_t r = threadIdx.x; r <= f.p; r += SF_NT) {
@@ -70,13 +78,22 @@ __global__ void __launch_bounds__(SF_NT) k_sf_search(SfArgs f) {
     if (r == 0) {
       res = 0;
     } else if (r < f.p) {
-      const uint64_t sp = sf_splitter(f.tree, f.lgp, r);
-      const uint32_t skey = (uint32_t)(sp >> 32);
-      const uint64_t stag = (uint32_t)sp;
+      KT skey;
+      uint64_t stag;
+      if constexpr (KW == 4) {
+        const uint64_t sp = sf_splitter(f.tree, f.lgp, r);
+        skey = (KT)(sp >> 32);
+        stag = (uint32_t)sp;
+      } else {
+        const uint32_t z = __builtin_ctz(r);
+        const uint32_t slot = (1u << (f.lgp - 1 - z)) + (r >> (z + 1));
+        skey = f.tree[slot];
+        stag = f.tree_tag[slot];
+      }
       uint32_t a = 0, z = len;   // first position whose key is above the splitter
       while (a < z) {
         const uint32_t m = (a + z) >> 1;
-        const uint32_t km = lds ? sk[m] : to_ord(f.bkeys[bs + m], f.kind);
+        const KT km = lds ? sk[m] : to_ord(bkeys[bs + m], f.kind);
         const bool upto = km < skey || (km == skey && bs + f.bidx[bs + m] <= stag);
         if (upto) a = m + 1;
         else z = m;
@@ -84,6 +101,69 @@ __global__ void __launch_bounds__(SF_NT) k_sf_search(SfArgs f) {
       res = a;
     }
     row[r] = res;
+  }
+}
+
+// Step 5 for any key and payload width: bucket j gathers its runs (block
+// order) with their payloads -- the caller's payload of each key, found
+// through its in-block index, or for an index payload that index -- into
+// the stage, and the buckets are then sorted as segments (stable, so equal
+// keys keep the gathered order, which is input order).  off[j] = start of
+// bucket j, off[p] = n.
+template <int KW, int VW>
+__global__ void __launch_bounds__(SF_GNT) k_sf_gather_any(SfArgs f, void* kstage, void* vstage, const void* vin,
+                                                          int iota, int64_t* off, uint64_t* exp_counts) {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  __shared__ uint32_t offs[SF_PMAX + 1];   // start of run k in the bucket
+  __shared__ uint32_t src[SF_PMAX];        // start of run k in the sorted blocks
+  __shared__ uint32_t red[2 * (SF_GNT / WAVE)];
+  const uint32_t j = blockIdx.x, p = f.p;
+  if (j >= p) return;
+  const int t = threadIdx.x;
+  const uint32_t per = (p + SF_GNT - 1) / SF_GNT;
+  const uint32_t k0 = min(p, (uint32_t)t * per), k1 = min(p, k0 + per);
+  uint32_t cnt = 0, below = 0;
+  for (uint32_t k = k0; k < k1; k++) {
+    const uint32_t* row = f.pos + (uint64_t)k * (p + 1);
+    const uint32_t a = row[j], b = row[j + 1];
+    src[k] = (uint32_t)sf_block_start(f.n, p, k) + a;
+    offs[k] = b - a;
+    cnt += b - a;
+    below += a;
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan<SF_GNT>(cnt, red, &tot);
+  __syncthreads();
+  for (uint32_t k = k0; k < k1; k++) {
+    const uint32_t l = offs[k];
+    offs[k] = run;
+    run += l;
+  }
+  if (t == 0) offs[p] = tot;
+  uint32_t start;
+  block_excl_scan<SF_GNT>(below, red, &start);
+  __syncthreads();
+  const KT* bkeys = (const KT*)f.bkeys;
+  for (uint32_t e = t; e < tot; e += SF_GNT) {
+    uint32_t a = 0, z = p;   // last run whose start is <= e
+    while (z - a > 1) {
+      const uint32_t m = (a + z) >> 1;
+      if (offs[m] <= e) a = m;
+      else z = m;
+    }
+    const uint32_t q = src[a] + (e - offs[a]);            // position in the sorted blocks
+    ((KT*)kstage)[start + e] = bkeys[q];
+    if constexpr (VW != 0) {
+      const uint64_t gi = sf_block_start(f.n, p, a) + f.bidx[q];   // input index of the key
+      ((VT*)vstage)[start + e] = iota ? (VT)gi : ((const VT*)vin)[gi];
+    }
+  }
+  if (t == 0) {
+    off[j] = start;
+    if (j == p - 1) off[p] = (int64_t)f.n;
+    f.bkt[j] = make_uint2(start, tot);
+    if (exp_counts) exp_counts[j] = tot;
   }
 }
 

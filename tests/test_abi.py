@@ -109,9 +109,11 @@ def test_bad_types_rejected():
 
 def test_sort_first_flag():
     """SS_F_SORT_FIRST (the organisation of Alg. 1 / Alg. 2: blocks sorted
-    first) takes 4-byte keys without payload, plans no level below, and
-    its workspace holds the sorted blocks (keys and in-block indices) and
-    the p x (p + 1) run table."""
+    first) plans no level below, and its workspace holds the sorted blocks
+    (keys and in-block indices) and the p x (p + 1) run table; 8-byte keys
+    and payloads plan the gathered buckets' segmented sort too, and the
+    pairwise merge of step 5 (SS_F_SF_MERGE) takes 4-byte keys without
+    payload only."""
     SF = N.SS_F_SORT_FIRST
     for kt in (N.SS_I32, N.SS_U32, N.SS_F32):
         rc, b = _ws(2**26, kt, p=4096, s=16, flags=SF)
@@ -119,9 +121,16 @@ def test_sort_first_flag():
         for mode in (0, 1):
             rc, info = _layout(2**22, kt, p=256, s=4, sampling=mode, flags=SF)
             assert rc == 0 and info.levels == 0 and info.p_eff == 256
-    assert _ws(2**20, N.SS_U64, flags=SF)[0] == N.SS_EINVAL
-    assert _ws(2**20, N.SS_I32, N.SS_V_B32, flags=SF)[0] == N.SS_EINVAL
-    assert "SORT_FIRST" in N.last_error()
+    for kt, vt in ((N.SS_U64, N.SS_V_NONE), (N.SS_I32, N.SS_V_B32), (N.SS_F64, N.SS_V_B64),
+                   (N.SS_I64, N.SS_V_IOTA64)):
+        rc, b = _ws(2**22, kt, vt, p=1024, s=8, flags=SF)
+        kw = 4 if kt in (N.SS_U32, N.SS_I32, N.SS_F32) else 8
+        # sorted blocks + in-block index, the stage, the run table
+        assert rc == 0 and b >= (2 * kw + 4) * 2**22 + 4 * 1024 * 1025
+        rc, info = _layout(2**22, kt, p=256, s=4, flags=SF)
+        assert rc == 0 and info.levels == 0 and info.p_eff == 256
+        assert _ws(2**22, kt, vt, p=1024, s=8, flags=SF | N.SS_F_SF_MERGE)[0] == N.SS_EINVAL
+        assert "SF_MERGE" in N.last_error()
 
 
 def _prm():

@@ -178,3 +178,97 @@ def test_sort_first_merge_full_size_in_place():
     api.sort_keys(kd, prm, out=kd, ws=ws)
     np.testing.assert_array_equal(kd.cpu().numpy(), want)
     assert api.status(ws) == ""
+
+
+# 8-byte keys and payloads: step 5 gathers each bucket's runs with the
+# payload of every key and sorts the p buckets as segments.
+
+def _keys64(n, kind, seed):
+    g = np.random.default_rng(seed)
+    if kind == "u64":
+        k = g.integers(0, 2**64 - 1, n, dtype=np.uint64, endpoint=True)
+        k[::9] = k[4]                            # duplicates across blocks
+    elif kind == "i64":
+        k = g.integers(-2**40, 2**40, n, dtype=np.int64)
+        k[::11] = -7
+    else:
+        k = g.standard_normal(n) * 1e6
+        k[::1000] = -0.0
+        k[1::1000] = 0.0
+        k[2::13] = 3.5
+    return k
+
+
+@pytest.mark.parametrize("kind", ["u64", "i64", "f64"])
+@pytest.mark.parametrize("mode,p,s", [(oracle.RANDOM, 1024, 8), (oracle.REGULAR, 256, 4), (oracle.RANDOM, 64, 16)])
+def test_sort_first_8byte_keys_counts(kind, mode, p, s):
+    """8-byte keys under both sampling rules: splitters and bucket counts
+    (sizes of the concatenated runs) equal the oracle's, the output is the
+    oracle's stable order bit for bit.  2^20 + 333 keys: ragged blocks; p =
+    64 gives blocks of 16K 8-byte keys, past the search's LDS copy."""
+    n = (1 << 20) + 333
+    keys = _keys64(n, kind, 100 + p + mode)
+    kd, kt = to_dev(keys)
+    sampling = "regular" if mode == oracle.REGULAR else "random"
+    prm = api.params(p=p, s=s, seed=23, sampling=sampling, flags=SF)
+    note(f"sort-first 8-byte {kind} mode={mode} p={p} s={s}")
+    out, st, info = api.stages(kd, prm, key_type=kt)
+    pe = oracle.p_eff(n, p, s, mode)
+    assert info.p_eff == pe
+    ref = oracle.stages(keys, pe, s, mode, 23)
+    np.testing.assert_array_equal(st["spl_ord"], ref["spl_ord"])
+    np.testing.assert_array_equal(st["spl_tag"], ref["spl_tag"])
+    np.testing.assert_array_equal(st["counts"], ref["counts"])
+    np.testing.assert_array_equal(to_host(out, keys.dtype).view(np.uint64), keys[ref["perm"]].view(np.uint64))
+
+
+@pytest.mark.parametrize("kdt,vform", [(np.int32, "b32"), (np.int32, "iota64"), (np.uint64, "b64"),
+                                       (np.float64, "iota32"), (np.uint64, "b32"), (np.float32, "b64")])
+@pytest.mark.parametrize("sampling", ["random", "regular"])
+def test_sort_first_pairs(kdt, vform, sampling):
+    """Pairs under sort-first: every payload width (stored 4 / 8 bytes, the
+    stable permutation as 32- or 64-bit index) with 4- and 8-byte keys.
+    Keys and payloads equal the oracle's stable order element by element."""
+    n = (1 << 21) + 4099
+    g = np.random.default_rng([np.dtype(kdt).itemsize, len(vform), int(vform[-2:]), len(sampling)])
+    if kdt in (np.float32, np.float64):
+        keys = g.standard_normal(n).astype(kdt)
+    elif kdt == np.int32:
+        keys = g.integers(-5000, 5000, n, dtype=np.int32)         # many equal keys
+    else:
+        keys = g.integers(0, 2**64 - 1, n, dtype=np.uint64, endpoint=True)
+        keys[::3] = keys[10]
+    kd, kt = to_dev(keys)
+    perm = oracle.stable_perm(keys)
+    prm = api.params(p=512, s=8, seed=9, sampling=sampling, flags=SF)
+    note(f"sort-first pairs {np.dtype(kdt).name} {vform} {sampling}")
+    if vform.startswith("iota"):
+        ko, vo = api.sort_pairs(kd, None, prm, iota="int32" if vform == "iota32" else "int64", key_type=kt)
+        np.testing.assert_array_equal(vo.cpu().numpy().astype(np.int64), perm)
+    else:
+        vdt = np.uint32 if vform == "b32" else np.uint64
+        vals = g.integers(0, np.iinfo(vdt).max, n, dtype=vdt, endpoint=True)
+        vd, _ = to_dev(vals)
+        ko, vo = api.sort_pairs(kd, vd, prm, key_type=kt)
+        np.testing.assert_array_equal(to_host(vo, vdt), vals[perm])
+    w = np.uint32 if np.dtype(kdt).itemsize == 4 else np.uint64
+    np.testing.assert_array_equal(to_host(ko, kdt).view(w), keys[perm].view(w))
+
+
+def test_sort_first_pairs_in_place_full_size():
+    """2^26 uint64 keys with a 4-byte payload (the duplicate-heavy pairs
+    workload: keys on [0, 0.7 n)), p = 4096, s = 16, keys and payload
+    sorted in place (keys_out == keys_in, vals_out == vals_in)."""
+    n = 1 << 26
+    keys, vals = workloads.pairs_dup(n, workloads.seed_for(3, 1))
+    vals ^= np.uint32(0x5A5A5A5A)
+    perm = oracle.stable_perm(keys)
+    kd, kt = to_dev(keys)
+    vd, _ = to_dev(vals)
+    prm = api.params(p=4096, s=16, seed=3, flags=SF)
+    ws = api._workspace(api.workspace_size(n, N.SS_U64, N.SS_V_B32, prm), kd.device)
+    note("sort-first pairs 2^26 u64/u32 in place")
+    api.sort_pairs(kd, vd, prm, keys_out=kd, vals_out=vd, ws=ws, key_type=kt)
+    np.testing.assert_array_equal(to_host(kd, np.uint64), keys[perm])
+    np.testing.assert_array_equal(to_host(vd, np.uint32), vals[perm])
+    assert api.status(ws) == ""
