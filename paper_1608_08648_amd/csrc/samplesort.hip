@@ -494,7 +494,7 @@ int plan_single_t(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
     P->o_wha_part = L.take(4 * (cdiv(na, SCAN_BLOCK) + 1));
     P->o_wkeys = L.take(4 * (size_t)p);
     P->o_wtags = L.take(4 * (size_t)p);
-    P->o_wcells = L.take(4 * (size_t)WIDE_CELLS);
+    P->o_wcells = L.take(4 * ((size_t)WIDE_CELLS + 1));
     P->o_whdr = L.take(sizeof(WideHdr));
     P->o_wcb = L.take(n);
   }
@@ -774,7 +774,11 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   uint32_t* pf = (uint32_t*)(ws + P.o_whf_part);
   uint32_t* pa = (uint32_t*)(ws + P.o_wha_part);
   LAUNCH(PK_TREE, k_wide_table, dim3(WIDE_TABLE_WG), dim3(NT), 0, st, w);
-  LAUNCH(PK_CLASSIFY, k_wide_count, dim3(w.W), dim3(NT), 0, st, w);
+  switch (P.ty.kind) {
+    case 0: LAUNCH(PK_CLASSIFY, k_wide_count<0>, dim3(w.W), dim3(NT), 0, st, w); break;
+    case 1: LAUNCH(PK_CLASSIFY, k_wide_count<1>, dim3(w.W), dim3(NT), 0, st, w); break;
+    default: LAUNCH(PK_CLASSIFY, k_wide_count<2>, dim3(w.W), dim3(NT), 0, st, w); break;
+  }
   LAUNCH_CHECK();
   const uint32_t nbf = (uint32_t)cdiv(nf, SCAN_BLOCK), nba = (uint32_t)cdiv(na, SCAN_BLOCK);
   // both count arrays in one set of scan launches

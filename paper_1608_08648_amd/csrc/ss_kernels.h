@@ -887,9 +887,19 @@ __global__ void __launch_bounds__(NT) k_scan_reduce(uint32_t* h, uint32_t* part,
   uint64_t b0 = (uint64_t)bid * SCAN_BLOCK;
   if (b0 >= total) return;
   uint32_t s = 0;
-  for (int r = 0; r < SCAN_ITEMS; r++) {
-    uint64_t i = b0 + (uint64_t)r * NT + threadIdx.x;
-    if (i < total) s += h[i];
+  if (b0 + SCAN_BLOCK <= total) {
+    // a whole block: 16-byte loads (every scanned array starts 16-byte aligned)
+    const uint4* hv = (const uint4*)(h + b0);
+#pragma unroll
+    for (int r = 0; r < SCAN_ITEMS / 4; r++) {
+      const uint4 v = hv[r * NT + threadIdx.x];
+      s += v.x + v.y + v.z + v.w;
+    }
+  } else {
+    for (int r = 0; r < SCAN_ITEMS; r++) {
+      uint64_t i = b0 + (uint64_t)r * NT + threadIdx.x;
+      if (i < total) s += h[i];
+    }
   }
   uint32_t tot;
   block_excl_scan<NT>(s, sh, &tot);
@@ -922,19 +932,41 @@ __global__ void __launch_bounds__(NT) k_scan_down(uint32_t* h, uint32_t* part, u
   uint64_t b0 = (uint64_t)bid * SCAN_BLOCK;
   if (b0 >= total) return;
   // thread t owns the SCAN_ITEMS consecutive entries starting at b0 + t*SCAN_ITEMS
+  static_assert(SCAN_ITEMS == 8, "two 16-byte vectors per thread");
+  const bool whole = b0 + SCAN_BLOCK <= total;
   uint32_t v[SCAN_ITEMS];
   uint32_t s = 0;
-  for (int k = 0; k < SCAN_ITEMS; k++) {
-    uint64_t i = b0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
-    v[k] = i < total ? h[i] : 0;
-    s += v[k];
+  if (whole) {
+    const uint4* hv = (const uint4*)(h + b0) + 2 * threadIdx.x;
+    const uint4 a = hv[0], b = hv[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+      uint64_t i = b0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
+      v[k] = i < total ? h[i] : 0;
+    }
   }
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; k++) s += v[k];
   uint32_t tot;
   uint32_t run = block_excl_scan<NT>(s, sh, &tot) + part[bid];
-  for (int k = 0; k < SCAN_ITEMS; k++) {
-    uint64_t i = b0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
-    if (i < total) h[i] = run;
-    run += v[k];
+  if (whole) {
+    uint32_t o[SCAN_ITEMS];
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+      o[k] = run;
+      run += v[k];
+    }
+    uint4* hv = (uint4*)(h + b0) + 2 * threadIdx.x;
+    hv[0] = make_uint4(o[0], o[1], o[2], o[3]);
+    hv[1] = make_uint4(o[4], o[5], o[6], o[7]);
+  } else {
+    for (int k = 0; k < SCAN_ITEMS; k++) {
+      uint64_t i = b0 + (uint64_t)threadIdx.x * SCAN_ITEMS + k;
+      if (i < total) h[i] = run;
+      run += v[k];
+    }
   }
 }
 

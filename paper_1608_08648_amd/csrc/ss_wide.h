@@ -100,8 +100,8 @@ struct WideArgs {
 // key} and U_j = L_{j+1}.  A key in cell j has between L_j and U_j
 // splitters below it; a binary search over those few candidates (about p
 // / cells of them for evenly spread keys) finds the count.
-constexpr int WIDE_CELL_BITS = 11;
-constexpr int WIDE_CELLS = 1 << WIDE_CELL_BITS;
+constexpr int WIDE_CELL_BITS = 13;
+constexpr int WIDE_CELLS = 1 << WIDE_CELL_BITS;   // (plus one sentinel cell past the range)
 constexpr int WIDE_TABLE_WG = 8;                 // work-groups building the table
 
 // One work-group: the sorted splitters (rank r in [1, p): key and tag) from
@@ -151,7 +151,8 @@ __global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
     }
     return a - 1;
   };
-  for (uint32_t j = g0; j < ncell; j += gs) w.cells[j] = L(j) | (L(j + 1) << 16);
+  // (cell ncell, past kmax, is the sentinel: every splitter below)
+  for (uint32_t j = g0; j <= ncell; j += gs) w.cells[j] = L(j) | (L(j + 1) << 16);
   if (g0 == 0) *w.hdr = WideHdr{kmin, kmax, sh, ncell};
 }
 
@@ -235,19 +236,28 @@ __device__ __forceinline__ void wide_load_b(uint32_t (&b)[U], const uint8_t* cb,
 }
 
 struct WideCountLds {
-  uint32_t sk[WIDE_PMAX];        // sorted splitter keys (rank 1..p-1)
-  uint32_t cells[WIDE_CELLS];
+  uint32_t sk[WIDE_PMAX + 2];    // sorted splitter keys (rank 1..p-1), then two all-ones sentinels
+  uint32_t cells[WIDE_CELLS + 1];
   uint32_t cnt[WIDE_PMAX / 2];   // non-tie keys per fine bucket, two 16-bit counts per word
   uint32_t ties[WIDE_PMAX];      // tie-low | tie-high << 16 (a tile holds < 2^16 keys)
   uint32_t csum[WIDE_P1];
-  WideHdr h;
 };
 
-// Per tile: classify every key (step 4) and count.  Runs of equal (kind,
-// bucket) in a thread's keys are added to the LDS counters at once.  (Six
-// waves per SIMD, three work-groups per CU: the LDS holds 16-bit counts and
-// no tags, the compiler keeps to 80 VGPRs.)
-__global__ void __launch_bounds__(NT, 6) k_wide_count(WideArgs w) {
+// Per tile: classify every key (step 4) and count.
+//
+// The common case is branch-free: a cell holds at most two splitter keys
+// for nearly every key (2^13 cells over the splitters' range), so the
+// key's count of splitters below it is L + [c1 < key] + [c2 < key] with
+// c1, c2 the next two splitter keys after the cell's first L.  Reading them
+// past the cell's last candidate is harmless: the next splitter's key lies
+// in a later cell, so above the key, and two all-ones sentinels follow the
+// last splitter.  The LDS reads of a thread's WIDE_U keys are issued
+// together.  Keys of crowded cells (more than two candidates) and tie keys
+// (equal to a splitter's key, which need the position) take the slower
+// exact paths, entered once per row of a wave that holds any.  (Two
+// work-groups per CU: 74 KB of LDS each.)
+template <int KIND>
+__global__ void __launch_bounds__(NT, 4) k_wide_count(WideArgs w) {
   __shared__ WideCountLds sm;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= w.W) return;
@@ -262,35 +272,48 @@ __global__ void __launch_bounds__(NT, 6) k_wide_count(WideArgs w) {
     sm.sk[k] = w.skeys[k];
     sm.ties[k] = 0;
   }
+  if (t < 2) sm.sk[p + t] = ~0u;
   for (uint32_t k = t; k < p / 2; k += NT) sm.cnt[k] = 0;
   const WideHdr h = *w.hdr;
-  for (uint32_t j = t; j < h.ncell; j += NT) sm.cells[j] = w.cells[j];
+  for (uint32_t j = t; j <= h.ncell; j += NT) sm.cells[j] = w.cells[j];
   if (t < (int)WIDE_P1) sm.csum[t] = 0;
   __syncthreads();
-  uint32_t cur = ~0u, run = 0;       // run of equal (kind << 16 | bucket)
   uint32_t hint = ~0u;               // bucket of this thread's previous tie key
-  auto flush = [&]() {
-    if (!run) return;
-    const uint32_t kind = cur >> 16, b = cur & 0xFFFFu;
-    if (kind == 0) atomicAdd(&sm.cnt[b >> 1], run << (16 * (b & 1)));
-    else atomicAdd(&sm.ties[b], kind == 1 ? run : run << 16);
-  };
+  const uint64_t all = __ballot(1);
   for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_CH) {
-    uint32_t key[WIDE_U];
+    uint32_t key[WIDE_U], cv[WIDE_U], c1[WIDE_U], c2[WIDE_U];
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) key[u] = to_ord(nk[u], w.kin);
+    for (int u = 0; u < WIDE_U; u++) key[u] = to_ord(nk[u], KIND);
     if (i0 + WIDE_CH < t1) wide_load(nk, src, i0 + WIDE_CH, t1);
+    // cell of every key (below the range: cell 0; above it: the sentinel
+    // cell, whose first count is p - 1)
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) {
+      const uint32_t d = max(key[u], h.kmin) - h.kmin;
+      cv[u] = sm.cells[min(d >> h.sh, h.ncell)];
+    }
+#pragma unroll
+    for (int u = 0; u < WIDE_U; u++) {
+      const uint32_t L = cv[u] & 0xFFFFu;
+      c1[u] = sm.sk[L + 1];
+      c2[u] = sm.sk[L + 2];
+    }
 #pragma unroll
     for (int u = 0; u < WIDE_U; u++) {
       const uint32_t i = i0 + u * NT + t;
-      if (i < t1) {
-        bool tie;
-        const uint32_t lo = wide_lower(sm.sk, sm.cells, h, p, key[u], tie);
-        w.cb[i] = tie ? (uint8_t)0xFFu : (uint8_t)((lo - 1) >> lg2);
-        uint32_t b = lo - 1, kind = 0;
-        if (tie) {
+      const bool valid = i < t1;
+      const uint32_t k = key[u];
+      const uint32_t L = cv[u] & 0xFFFFu, len = (cv[u] >> 16) - L;
+      uint32_t b = L + (c1[u] < k ? 1u : 0u) + (c2[u] < k ? 1u : 0u);   // splitters below the key
+      bool tie = (c1[u] == k && len >= 1) || (c2[u] == k && len >= 2);
+      if (__ballot(valid && len > 2)) {
+        if (valid && len > 2) b = wide_lower(sm.sk, sm.cells, h, p, k, tie) - 1;
+      }
+      uint32_t kind = 0;
+      if (__ballot(valid && tie)) {
+        if (valid && tie) {
           // equal keys in input order mostly share a bucket: try the last one
-          const uint32_t k = key[u];
+          const uint32_t lo = b + 1;   // the first splitter with key >= k (it has key k)
           const uint32_t hb = hint;
           bool hit = false;
           if (hb != ~0u && hb + 1 >= lo) {
@@ -308,17 +331,24 @@ __global__ void __launch_bounds__(NT, 6) k_wide_count(WideArgs w) {
           }
           hint = b;
         }
-        const uint32_t idx = (kind << 16) | b;
-        if (idx != cur) {
-          flush();
-          cur = idx;
-          run = 0;
+      }
+      if (valid) w.cb[i] = tie ? (uint8_t)0xFFu : (uint8_t)(b >> lg2);
+      // count: one atomic for a row of one (kind, bucket) (sorted or
+      // constant input), else one per key
+      const uint32_t idx = (kind << 16) | b;
+      const uint32_t f = __builtin_amdgcn_readfirstlane(idx);
+      if (__ballot(valid && idx == f) == all) {
+        if (t % WAVE == 0) {
+          const uint32_t run = (uint32_t)__popcll(all);
+          if (kind == 0) atomicAdd(&sm.cnt[b >> 1], run << (16 * (b & 1)));
+          else atomicAdd(&sm.ties[b], kind == 1 ? run : run << 16);
         }
-        run++;
+      } else if (valid) {
+        if (kind == 0) atomicAdd(&sm.cnt[b >> 1], 1u << (16 * (b & 1)));
+        else atomicAdd(&sm.ties[b], kind == 1 ? 1u : 1u << 16);
       }
     }
   }
-  flush();
   __syncthreads();
   const uint32_t R = w.W + 2;
   for (uint32_t b = t; b < p; b += NT) {
