@@ -390,6 +390,7 @@ struct Plan {
   // a large sample of 4-byte keys: packed records and the nested sort that orders them
   Plan* nested_s = nullptr;
   size_t o_spack = 0, o_nested_s = 0;
+  size_t o_scnt = 0;       // 4-byte big sample ranked by chunk pairs: the counts
   // segmented without user parameters: the tuning table's p and s per size class
   bool use_tab = false;
   TuneTab tab{};
@@ -522,6 +523,12 @@ int plan_single_t(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
     if (rc) return rc;
     P->o_spack = L.take(8 * P->m);
     P->o_nested_s = L.take(P->nested_s->bytes);
+  } else if (ty.KW == 4 && P->lp.big_sample) {
+    // the sorted chunks' records also packed as ord << 32 | tag, for the rank
+    // pass; up to SAMPLE_PAIR_MAXCH chunks, 16-bit counts per (chunk, record)
+    P->o_spack = L.take(8 * P->m);
+    const uint64_t nch = cdiv(P->m, sample_chunk(4));
+    if (nch <= SAMPLE_PAIR_MAXCH) P->o_scnt = L.take(2 * nch * P->m);
   }
   if (P->sortfirst) {
     P->o_sfpos = L.take(4 * (size_t)p * (p + 1));
@@ -695,6 +702,8 @@ LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void*
   a.vtmp = vtmp;
   a.s_ord = ws + lv.o_sord;
   a.s_tag = (uint32_t*)(ws + lv.o_stag);
+  a.s_pack = (l == 0 && P.ty.KW == 4 && P.lp.big_sample && !P.nested_s && P.o_spack)
+                 ? (uint64_t*)(ws + P.o_spack) : nullptr;
   a.tree = ws + lv.o_tree;
   a.tree_tag = lv.o_ttag ? (uint32_t*)(ws + lv.o_ttag) : nullptr;
   a.hist = (uint32_t*)(ws + lv.o_hist);
@@ -933,7 +942,20 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       const uint32_t ch = sample_chunk(KW);
       LAUNCH(PK_SAMPLE_SORT, k_sample_chunk_sort<KW>, dim3((uint32_t)cdiv(P.m, ch)), dim3(NT), 0, st, a);
       LAUNCH_CHECK();
-      LAUNCH(PK_SAMPLE_MERGE, k_sample_rank<KW>, dim3((uint32_t)cdiv(P.m, 256)), dim3(256), 0, st, a, exp);
+      const uint64_t nch = cdiv(P.m, ch);
+      if (KW == 4 && P.o_scnt) {
+        uint16_t* cnt = (uint16_t*)(ws + P.o_scnt);
+        LAUNCH(PK_SAMPLE_MERGE, k_sample_pair_count, dim3((uint32_t)(nch * nch)), dim3(NT), 0, st, a, cnt);
+        LAUNCH_CHECK();
+        LAUNCH(PK_SAMPLE_MERGE, k_sample_rank_sum, dim3((uint32_t)cdiv(P.m, 256)), dim3(256), 0, st, a,
+               (const uint16_t*)cnt, exp);
+      } else {
+        // lanes per record: the chunk count rounded up to a power of two, at most a wave
+        uint32_t lgL = 0;
+        while ((1ull << lgL) < nch && lgL < 6) lgL++;
+        LAUNCH(PK_SAMPLE_MERGE, k_sample_rank<KW>, dim3((uint32_t)cdiv(P.m << lgL, 256)), dim3(256), 0, st, a,
+               exp, lgL);
+      }
     } else {
       LAUNCH(PK_SAMPLE_SORT, k_sample_sort_wg<KW>, dim3(lv.seg_cap), dim3(NT), 0, st, a, exp);
     }

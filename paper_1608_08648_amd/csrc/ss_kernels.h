@@ -52,9 +52,11 @@ template <int KW> struct SampleCap {
 // work-group, then merged (4-byte keys: small chunks, so many work-groups
 // share the sort).
 template <int KW> struct SampleChunk {
-  static constexpr int K = (KW == 4) ? 8 : SampleCap<KW>::KMAX;
+  static constexpr int K = (KW == 4) ? 4 : SampleCap<KW>::KMAX;
   static constexpr int C = NT * K;
 };
+// 4-byte samples of up to this many chunks are ranked by chunk pairs
+constexpr uint32_t SAMPLE_PAIR_MAXCH = 64;
 
 // Keys per thread in one chunk of the stable split.
 template <int KW, int VW, int PMAX = 256> struct SplitChunk {
@@ -129,6 +131,7 @@ struct LevelArgs {
   void* vtmp;
   void* s_ord;             // sample key images (KW bytes each)
   uint32_t* s_tag;         // sample tags
+  uint64_t* s_pack;        // 4-byte keys, sorted sample chunks: (ord << 32) | tag per record, or null
   void* tree;              // splitter trees
   uint32_t* tree_tag;      // tags of the tree (8-byte keys)
   uint32_t* hist;          // counts, then offsets (in place)
@@ -565,6 +568,7 @@ __device__ __forceinline__ void sample_sort_one(const LevelArgs& a, const SegDes
       const uint64_t x = sm.xh[i];
       ((KT*)a.s_ord)[d.samp_off + i] = (KT)(x >> 32);
       a.s_tag[d.samp_off + i] = (uint32_t)x;
+      if (a.s_pack) a.s_pack[d.samp_off + i] = x;
       if (exp) { a.exp_smp_ord[i] = x >> 32; a.exp_smp_tag[i] = (uint32_t)x; }
     }
     for (uint32_t k = 1 + t; k < d.p; k += NT) {
@@ -665,34 +669,65 @@ __global__ void __launch_bounds__(NT) k_sample_chunk_sort(LevelArgs a) {
 // multiple of the stride below p * stride is splitter rank / stride (step
 // 3) and goes to its slot of the implicit tree; with the stage export on
 // every record is also written at its rank.
+//
+// 2^lgL lanes (aligned inside a wave, lgL <= 6) serve one record: lane j
+// searches chunks j, j + 2^lgL, ..., and a butterfly sum over the group
+// adds the counts, so the dependent reads of the binary searches are spread
+// over many waves instead of one thread's long chain.
 template <int KW>
-__global__ void __launch_bounds__(256) k_sample_rank(LevelArgs a, int export_stages) {
+__global__ void __launch_bounds__(256) k_sample_rank(LevelArgs a, int export_stages, uint32_t lgL) {
   using KT = typename KeyOf<KW>::T;
   constexpr uint32_t C = SampleChunk<KW>::C;
   const SegDesc d = a.segs[0];
-  const uint32_t g = blockIdx.x * 256 + threadIdx.x;
-  if (g >= d.m) return;
+  const uint64_t gt = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t L = 1u << lgL;
+  const uint64_t g64 = gt >> lgL;
+  const uint32_t lane = (uint32_t)gt & (L - 1);
+  const bool live = g64 < d.m;
+  const uint32_t g = live ? (uint32_t)g64 : 0u;
   const KT* so = (const KT*)a.s_ord + d.samp_off;
   const uint32_t* st = a.s_tag + d.samp_off;
-  const KT k = so[g];
-  const uint32_t tg = st[g];
-  const uint32_t c = g / C, nch = (d.m + C - 1) / C;
-  uint32_t rank = g - c * C;
-  for (uint32_t j = 0; j < nch; j++) {
-    if (j == c) continue;
-    const uint32_t b = j * C, len = min(C, d.m - b);
-    const bool le = j < c;                    // count records <= (k, tg), else < (k, tg)
-    uint32_t lo = 0, hi = len;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      const KT ok = so[b + mid];
-      const uint32_t ot = st[b + mid];
-      const bool before = ok < k || (ok == k && (le ? ot <= tg : ot < tg));
-      if (before) lo = mid + 1;
-      else hi = mid;
+  KT k = 0;
+  uint32_t tg = 0, cnt = 0;
+  if (live) {
+    k = so[g];
+    tg = st[g];
+    const uint32_t c = g / C, nch = (d.m + C - 1) / C;
+    // 4-byte keys with the packed copy: one 8-byte read per search step
+    const uint64_t* pk = KW == 4 ? a.s_pack : nullptr;
+    const uint64_t me = ((uint64_t)k << 32) | tg;
+    for (uint32_t j = lane; j < nch; j += L) {
+      if (j == c) {
+        cnt += g - c * C;
+        continue;
+      }
+      const uint32_t b = j * C, len = min(C, d.m - b);
+      const bool le = j < c;                  // count records <= (k, tg), else < (k, tg)
+      uint32_t lo = 0, hi = len;
+      if (pk) {
+        const uint64_t* q = pk + d.samp_off + b;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          const uint64_t x = q[mid];
+          if (le ? x <= me : x < me) lo = mid + 1;
+          else hi = mid;
+        }
+      } else {
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          const KT ok = so[b + mid];
+          const uint32_t ot = st[b + mid];
+          const bool before = ok < k || (ok == k && (le ? ot <= tg : ot < tg));
+          if (before) lo = mid + 1;
+          else hi = mid;
+        }
+      }
+      cnt += lo;
     }
-    rank += lo;
   }
+  for (uint32_t o = L >> 1; o > 0; o >>= 1) cnt += __shfl_xor(cnt, (int)o, WAVE);
+  if (!live || lane != 0) return;
+  const uint32_t rank = cnt;
   const bool exp = export_stages != 0;
   if (exp) {
     a.exp_smp_ord[rank] = (uint64_t)k;
@@ -705,6 +740,96 @@ __global__ void __launch_bounds__(256) k_sample_rank(LevelArgs a, int export_sta
       const uint32_t z = __builtin_ctz(r);
       const uint32_t slot = (1u << (d.lgp - 1 - z)) + (r >> (z + 1));
       put_tree<KW>(a, d, slot, k, tg, exp);
+    }
+  }
+}
+
+// The same ranks for a 4-byte sample of at most SAMPLE_PAIR_MAXCH chunks,
+// in two launches.  First one work-group per ordered pair of chunks (c, j),
+// j != c: chunk j's packed records (ord << 32 | tag, whose order is the
+// records' order) are staged in LDS and every record of chunk c counts
+// those before it by a binary search there (<= for an earlier chunk, < for
+// a later one): cnt[j * m + g] for record g of chunk c.
+__global__ void __launch_bounds__(NT) k_sample_pair_count(LevelArgs a, uint16_t* cnt) {
+  constexpr uint32_t C = SampleChunk<4>::C;
+  constexpr int KR = SampleChunk<4>::K;           // records of chunk c per thread
+  static_assert((C & (C - 1)) == 0, "power-of-two chunks");
+  __shared__ uint64_t sj[C];
+  const SegDesc d = a.segs[0];
+  const uint32_t m = d.m, nch = (m + C - 1) / C;
+  const uint32_t c = blockIdx.x / nch, j = blockIdx.x % nch;
+  if (c >= nch || j == c) return;
+  const int t = threadIdx.x;
+  const uint64_t* q = a.s_pack + d.samp_off;
+  const uint32_t cb = c * C, clen = min(C, m - cb), jb = j * C, jlen = min(C, m - jb);
+  // chunk j to LDS, padded with all-ones records (above every record: a tag
+  // is a position below 2^32 - 1), and this thread's KR records of chunk c
+  uint64_t v[KR], x[KR];
+#pragma unroll
+  for (int r = 0; r < KR; r++) {
+    const uint32_t i = r * NT + t;
+    v[r] = i < jlen ? q[jb + i] : ~0ull;
+    const uint32_t ic = t * KR + r;
+    x[r] = ic < clen ? q[cb + ic] : 0ull;
+  }
+#pragma unroll
+  for (int r = 0; r < KR; r++) sj[r * NT + t] = v[r];
+  __syncthreads();
+  const bool le = j < c;
+  // records of chunk j before x: the predicate holds on a prefix of sj;
+  // fixed-step binary lifting, the KR searches side by side
+  uint32_t pos[KR];
+#pragma unroll
+  for (int r = 0; r < KR; r++) pos[r] = 0;
+  for (uint32_t b = C; b > 0; b >>= 1) {
+#pragma unroll
+    for (int r = 0; r < KR; r++) {
+      const uint32_t at = pos[r] + b;
+      const uint64_t y = sj[min(at, C) - 1];
+      const bool before = le ? y <= x[r] : y < x[r];
+      pos[r] = (at <= C && before) ? at : pos[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < KR; r++) {
+    const uint32_t ic = t * KR + r;
+    if (ic < clen) cnt[(uint64_t)j * m + cb + ic] = (uint16_t)pos[r];
+  }
+}
+
+// Second launch: rank of record g = its index in its chunk plus its counts
+// in the other chunks; splitters to the tree, records to the stage export.
+__global__ void __launch_bounds__(256) k_sample_rank_sum(LevelArgs a, const uint16_t* cnt, int export_stages) {
+  constexpr uint32_t C = SampleChunk<4>::C;
+  const SegDesc d = a.segs[0];
+  const uint32_t g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= d.m) return;
+  const uint32_t m = d.m, nch = (m + C - 1) / C, c = g / C;
+  uint32_t rank = g - c * C;
+  for (uint32_t j0 = 0; j0 < nch; j0 += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const uint32_t j = j0 + u;
+      v[u] = (j < nch && j != c) ? (uint32_t)cnt[(uint64_t)j * m + g] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) rank += v[u];
+  }
+  const uint64_t x = a.s_pack[d.samp_off + g];
+  const uint32_t k = (uint32_t)(x >> 32), tg = (uint32_t)x;
+  const bool exp = export_stages != 0;
+  if (exp) {
+    a.exp_smp_ord[rank] = (uint64_t)k;
+    a.exp_smp_tag[rank] = tg;
+  }
+  const uint32_t r1 = rank + 1;
+  if (r1 % d.stride == 0) {
+    const uint32_t r = r1 / d.stride;         // splitter rank, 1-based
+    if (r >= 1 && r < d.p) {
+      const uint32_t z = __builtin_ctz(r);
+      const uint32_t slot = (1u << (d.lgp - 1 - z)) + (r >> (z + 1));
+      put_tree<4>(a, d, slot, k, tg, exp);
     }
   }
 }
