@@ -49,7 +49,8 @@ constexpr int WIDE_CH = WIDE_U * NT;
 constexpr int WIDE_UA = 8;                      // keys per thread per chunk of the second pass (LDS)
 constexpr int WIDE_UA1 = 16;                    // keys per thread per chunk of the first pass (LDS)
 constexpr uint32_t WIDE_TILE = 7 * WIDE_U * 512; // keys per input tile (< 2^16: 16-bit tie counters)
-constexpr uint32_t WIDE_TB = 65536;            // nominal keys per piece of the second pass
+constexpr uint32_t WIDE_TB = 24576;            // nominal keys per piece of the second pass (small pieces: the
+                                               // work-groups finish together)
 // bucket sort of the wide split: 1024 threads, 30720 keys per round in LDS
 // (one work-group per CU), buckets of up to 65535 keys
 constexpr int WIDE_BNT = 1024;
