@@ -197,9 +197,21 @@ struct TreeLds;
 template <int PMAX>
 struct TreeLds<4, PMAX> {
   uint64_t node[PMAX];
+  // (every load issued before the first LDS store)
   __device__ void load(const void* tree, const uint32_t*, uint32_t off, uint32_t p) {
+    constexpr int R = (PMAX + NT - 1) / NT;
     const uint64_t* t = (const uint64_t*)tree + off;
-    for (uint32_t k = threadIdx.x; k < p; k += NT) node[k] = t[k];
+    uint64_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const uint32_t k = r * NT + threadIdx.x;
+      v[r] = k < p ? t[k] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const uint32_t k = r * NT + threadIdx.x;
+      if (k < p) node[k] = v[r];
+    }
   }
   // bucket = #{splitters < (ord, tag)}: walk lgp levels from the root
   __device__ __forceinline__ uint32_t classify(uint32_t ord, uint32_t tag, uint32_t lgp, uint32_t p) const {
@@ -228,8 +240,24 @@ struct TreeLds<8, PMAX> {
   uint64_t node[PMAX];
   uint32_t tag[PMAX];
   __device__ void load(const void* tree, const uint32_t* ttag, uint32_t off, uint32_t p) {
+    constexpr int R = (PMAX + NT - 1) / NT;
     const uint64_t* t = (const uint64_t*)tree + off;
-    for (uint32_t k = threadIdx.x; k < p; k += NT) { node[k] = t[k]; tag[k] = ttag[off + k]; }
+    uint64_t v[R];
+    uint32_t g[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const uint32_t k = r * NT + threadIdx.x;
+      v[r] = k < p ? t[k] : 0ull;
+      g[r] = k < p ? ttag[off + k] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      const uint32_t k = r * NT + threadIdx.x;
+      if (k < p) {
+        node[k] = v[r];
+        tag[k] = g[r];
+      }
+    }
   }
   __device__ __forceinline__ uint32_t classify(uint64_t ord, uint32_t tg, uint32_t lgp, uint32_t p) const {
     uint32_t k = 1;

@@ -126,14 +126,30 @@ __global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
       w.ha[(uint64_t)WIDE_P1 * w.W] = 0;
     }
   }
-  for (uint32_t r = threadIdx.x + 1; r < p; r += NT) {
-    const uint32_t z = __builtin_ctz(r);
-    const uint32_t k = (1u << (w.lgp - 1 - z)) + (r >> (z + 1));
-    const uint64_t nd = w.tree[k];
-    sk[r] = (uint32_t)(nd >> 32);
-    if (blockIdx.x == 0) {
-      w.skeys[r] = (uint32_t)(nd >> 32);
-      w.stags[r] = (uint32_t)nd;
+  {
+    // splitter of rank r from its tree slot (every load issued first)
+    constexpr int R = WIDE_PMAX / NT;
+    uint64_t nd[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+      const uint32_t r = q * NT + threadIdx.x + 1;
+      uint32_t k = 1;
+      if (r < p) {
+        const uint32_t z = __builtin_ctz(r);
+        k = (1u << (w.lgp - 1 - z)) + (r >> (z + 1));
+      }
+      nd[q] = r < p ? w.tree[k] : 0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+      const uint32_t r = q * NT + threadIdx.x + 1;
+      if (r < p) {
+        sk[r] = (uint32_t)(nd[q] >> 32);
+        if (blockIdx.x == 0) {
+          w.skeys[r] = (uint32_t)(nd[q] >> 32);
+          w.stags[r] = (uint32_t)nd[q];
+        }
+      }
     }
   }
   __syncthreads();
@@ -269,14 +285,39 @@ __global__ void __launch_bounds__(NT, 4) k_wide_count(WideArgs w) {
   uint32_t nk[WIDE_U];
   wide_load(nk, src, t0, t1);
   const uint32_t* stg = w.stags;   // tags: only tie keys read them (from L2)
-  for (uint32_t k = t; k < p; k += NT) {
-    sm.sk[k] = w.skeys[k];
-    sm.ties[k] = 0;
+  // the splitter keys and the cell table: every load issued before the
+  // first LDS store (one round trip, not one per loop step)
+  {
+    constexpr int RS = WIDE_PMAX / NT, RC = (WIDE_CELLS + 1 + NT - 1) / NT;
+    const WideHdr h0 = *w.hdr;
+    uint32_t vs[RS], vc[RC];
+#pragma unroll
+    for (int r = 0; r < RS; r++) {
+      const uint32_t k = r * NT + t;
+      vs[r] = k < p ? w.skeys[k] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < RC; r++) {
+      const uint32_t j = r * NT + t;
+      vc[r] = j <= h0.ncell ? w.cells[j] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < RS; r++) {
+      const uint32_t k = r * NT + t;
+      if (k < p) {
+        sm.sk[k] = vs[r];
+        sm.ties[k] = 0;
+      }
+      if (k < p / 2) sm.cnt[k] = 0;
+    }
+#pragma unroll
+    for (int r = 0; r < RC; r++) {
+      const uint32_t j = r * NT + t;
+      if (j <= h0.ncell) sm.cells[j] = vc[r];
+    }
   }
   if (t < 2) sm.sk[p + t] = ~0u;
-  for (uint32_t k = t; k < p / 2; k += NT) sm.cnt[k] = 0;
   const WideHdr h = *w.hdr;
-  for (uint32_t j = t; j <= h.ncell; j += NT) sm.cells[j] = w.cells[j];
   if (t < (int)WIDE_P1) sm.csum[t] = 0;
   __syncthreads();
   uint32_t hint = ~0u;               // bucket of this thread's previous tie key
