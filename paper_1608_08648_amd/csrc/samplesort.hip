@@ -861,6 +861,12 @@ template <int KW, int VW>
 int run_segmented(const Plan& P, char* ws, const void* in, const void* vin, void* out, void* vout,
                   const int64_t* off, hipStream_t st);
 
+// The top level of a single sort with random sampling whose 4-byte sample
+// is ranked by chunk pairs: init, draw and chunk sorts are one launch.
+bool fused_top(const Plan& P) {
+  return !P.segmented && !P.regular && P.ty.KW == 4 && P.lp.big_sample && !P.nested_s && P.o_scnt != 0;
+}
+
 // Sort-first organisation for 8-byte keys or with a payload: step 4 as
 // above; step 5 gathers bucket j's runs (with the payload of each key) into
 // the stage and sorts the p buckets as segments into the output.
@@ -907,7 +913,13 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       LAUNCH_CHECK();
     }
     // sample
-    if (l == 0 && P.regular) {
+    if (l == 0 && fused_top(P)) {
+      // init, draw and chunk sorts in one launch, then the pair ranks
+      TopInit ti{P.n, P.prm.seed, P.p_eff, (uint32_t)P.m, P.stride, P.lp.lv[0].tile};
+      LAUNCH(PK_SAMPLE_SORT, k_sample_draw_sort, dim3((uint32_t)cdiv(P.m, sample_chunk(4))), dim3(NT), 0, st, a,
+             (Ctl*)(ws + P.o_ctl), (SegDesc*)(ws + P.lp.lv[0].o_segs), ti);
+      LAUNCH_CHECK();
+    } else if (l == 0 && P.regular) {
       const uint32_t S = P.s * P.p_eff;
       LAUNCH(PK_SAMPLE, k_sample_regular<KW>, dim3(grid_of(P.m, 256, 4096)), dim3(256), 0, st, a,
                          (const void*)(ws + P.o_regk), (const uint32_t*)(ws + P.o_regi), (uint64_t)P.n, P.p_eff, S);
@@ -940,8 +952,10 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
       // sorted chunks, then every record's rank among all of them: the
       // splitters go straight to the tree
       const uint32_t ch = sample_chunk(KW);
-      LAUNCH(PK_SAMPLE_SORT, k_sample_chunk_sort<KW>, dim3((uint32_t)cdiv(P.m, ch)), dim3(NT), 0, st, a);
-      LAUNCH_CHECK();
+      if (!fused_top(P)) {
+        LAUNCH(PK_SAMPLE_SORT, k_sample_chunk_sort<KW>, dim3((uint32_t)cdiv(P.m, ch)), dim3(NT), 0, st, a);
+        LAUNCH_CHECK();
+      }
       const uint64_t nch = cdiv(P.m, ch);
       if (KW == 4 && P.o_scnt) {
         uint16_t* cnt = (uint16_t*)(ws + P.o_scnt);
@@ -1087,9 +1101,12 @@ int run_single(const Plan& P, char* ws, const void* in, const void* vin, void* o
     int rc = run_segmented<KW, 4>(*P.nested, ws + P.o_nested, in, nullptr, ws + P.o_regk, ws + P.o_regi, boff, st);
     if (rc) return rc;
   }
-  LAUNCH(PK_INIT, k_init_single, dim3(1), dim3(64), 0, st, g, (SegDesc*)(ws + P.lp.lv[0].o_segs), (uint64_t)P.n,
-                     P.p_eff, (uint32_t)P.m, P.stride, P.prm.seed, P.lp.lv[0].tile);
-  LAUNCH_CHECK();
+  // (the fused sample kernel initialises the level itself)
+  if (!fused_top(P)) {
+    LAUNCH(PK_INIT, k_init_single, dim3(1), dim3(64), 0, st, g, (SegDesc*)(ws + P.lp.lv[0].o_segs), (uint64_t)P.n,
+           P.p_eff, (uint32_t)P.m, P.stride, P.prm.seed, P.lp.lv[0].tile);
+    LAUNCH_CHECK();
+  }
   return run_levels<KW, VW>(P, ws, in, vin, out, vout, st);
 }
 

@@ -688,6 +688,46 @@ __global__ void __launch_bounds__(NT) k_sample_chunk_sort(LevelArgs a) {
   (void)sizeof(KT);
 }
 
+// The top level of a single sort whose 4-byte sample is ranked by chunk
+// pairs, in one launch: work-group 0 also writes the level's descriptor and
+// counters (as k_init_single), and every work-group draws its chunk of the
+// sample itself -- record j is the key at position floor(r_j * n / 2^64),
+// r_j the j-th output of the seeded generator, as k_sample_random draws it
+// (Alg. 2 step 2) -- then sorts the chunk by (key, position) and writes the
+// packed records the rank pass reads.
+struct TopInit {
+  uint64_t n, seed;
+  uint32_t p, m, stride, tile;
+};
+__device__ __forceinline__ void init_single(Ctl* g, SegDesc* segs, uint64_t n, uint32_t p, uint32_t m,
+                                            uint32_t stride, uint64_t seed, uint32_t tile);
+
+__global__ void __launch_bounds__(NT) k_sample_draw_sort(LevelArgs a, Ctl* g, SegDesc* segs, TopInit ti) {
+  __shared__ SampleLds<4> sm;
+  constexpr int K = SampleChunk<4>::K;
+  constexpr uint32_t C = SampleChunk<4>::C;
+  if (blockIdx.x == 0 && threadIdx.x == 0) init_single(g, segs, ti.n, ti.p, ti.m, ti.stride, ti.seed, ti.tile);
+  const uint32_t cb = blockIdx.x * C;
+  if (cb >= ti.m) return;
+  const uint32_t len = min(C, ti.m - cb);
+  const int t = threadIdx.x;
+  const uint32_t* src = (const uint32_t*)a.src;
+  uint64_t pos[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const uint32_t i = t * K + k;
+    pos[k] = i < len ? scale_to(sm64_at(ti.seed, cb + i), ti.n) : 0ull;
+  }
+  uint64_t v[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const uint32_t i = t * K + k;
+    v[k] = i < len ? (((uint64_t)to_ord(src[pos[k]], a.kin) << 32) | (uint32_t)pos[k]) : ~0ull;
+  }
+  block_merge_sort_u64<NT, K>(v, sm.xh);
+  for (uint32_t i = t; i < len; i += NT) a.s_pack[cb + i] = sm.xh[i];
+}
+
 // Sorted chunks of a large sample to splitters in one pass: the rank of a
 // record among all m records is its index in its own (sorted) chunk plus,
 // for every other chunk, the number of that chunk's records before it in
@@ -1664,9 +1704,9 @@ __global__ void __launch_bounds__(NT) k_bucket_leftover_keys(LevelArgs a, int li
 // Zero the control block and write the single top-level segment, planned
 // (the offsets and totals the level-planning kernel would give one segment
 // of n keys split into p buckets over tiles of `tile` keys).
-__global__ void k_init_single(Ctl* g, SegDesc* segs, uint64_t n, uint32_t p, uint32_t m, uint32_t stride,
-                              uint64_t seed, uint32_t tile) {
-  if (threadIdx.x == 0) {
+__device__ __forceinline__ void init_single(Ctl* g, SegDesc* segs, uint64_t n, uint32_t p, uint32_t m,
+                                            uint32_t stride, uint64_t seed, uint32_t tile) {
+  {
     *g = Ctl{};
     SegDesc d = {};
     d.beg = 0;
@@ -1689,6 +1729,11 @@ __global__ void k_init_single(Ctl* g, SegDesc* segs, uint64_t n, uint32_t p, uin
     c.keys = n;
     c.bucket_keys = 0;
   }
+}
+
+__global__ void k_init_single(Ctl* g, SegDesc* segs, uint64_t n, uint32_t p, uint32_t m, uint32_t stride,
+                              uint64_t seed, uint32_t tile) {
+  if (threadIdx.x == 0) init_single(g, segs, n, p, m, stride, seed, tile);
 }
 
 __global__ void k_init_ctl(Ctl* g) {

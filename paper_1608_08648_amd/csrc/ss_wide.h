@@ -111,6 +111,7 @@ constexpr int WIDE_TABLE_WG = 8;                 // work-groups building the tab
 // its share of the tie entries and the cells; work-group 0 writes the rest)
 __global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
   __shared__ uint32_t sk[WIDE_PMAX];
+  __shared__ uint16_t Ls[WIDE_CELLS + 2];
   const uint32_t p = w.p;
   const uint32_t g0 = blockIdx.x * NT + threadIdx.x, gs = gridDim.x * NT;
   // tie entries and the trailing totals of both count arrays start at zero
@@ -157,19 +158,22 @@ __global__ void __launch_bounds__(NT) k_wide_table(WideArgs w) {
   const int bw = bit_width<uint32_t>(kmax - kmin);
   const uint32_t sh = bw > WIDE_CELL_BITS ? (uint32_t)(bw - WIDE_CELL_BITS) : 0u;
   const uint32_t ncell = ((kmax - kmin) >> sh) + 1;
-  // L(j) = #{r : sk[r] < kmin + (j << sh)}, with 64-bit cell starts
-  auto L = [&](uint32_t j) -> uint32_t {
-    const uint64_t x = (uint64_t)kmin + ((uint64_t)j << sh);
-    uint32_t a = 1, z = p;                  // first r in [1, p) with sk[r] >= x, or p
-    while (a < z) {
-      uint32_t m = (a + z) / 2;
-      if ((uint64_t)sk[m] < x) a = m + 1;
-      else z = m;
-    }
-    return a - 1;
+  // L(j) = #{r : sk[r] < kmin + (j << sh)} = #{r : cell(r) < j}, cell(r) =
+  // (sk[r] - kmin) >> sh non-decreasing in r: splitter r sets L(j) = r - 1
+  // on the cells (cell(r-1), cell(r)] (cell(0) = -1; r = p covers the rest
+  // up to ncell + 1).  Cell ncell, past kmax, is the sentinel: every
+  // splitter below.
+  auto cell_of = [&](uint32_t r) -> int64_t {
+    if (r == 0) return -1;
+    if (r >= p) return (int64_t)ncell + 1;
+    return (int64_t)((sk[r] - kmin) >> sh);
   };
-  // (cell ncell, past kmax, is the sentinel: every splitter below)
-  for (uint32_t j = g0; j <= ncell; j += gs) w.cells[j] = L(j) | (L(j + 1) << 16);
+  for (uint32_t r = threadIdx.x + 1; r <= p; r += NT) {
+    const int64_t c0 = cell_of(r - 1), c1 = cell_of(r);
+    for (int64_t j = c0 + 1; j <= c1; j++) Ls[j] = (uint16_t)(r - 1);
+  }
+  __syncthreads();
+  for (uint32_t j = g0; j <= ncell; j += gs) w.cells[j] = (uint32_t)Ls[j] | ((uint32_t)Ls[j + 1] << 16);
   if (g0 == 0) *w.hdr = WideHdr{kmin, kmax, sh, ncell};
 }
 
