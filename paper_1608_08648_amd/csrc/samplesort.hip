@@ -784,9 +784,9 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   uint32_t* pa = (uint32_t*)(ws + P.o_wha_part);
   LAUNCH(PK_TREE, k_wide_table, dim3(WIDE_TABLE_WG), dim3(NT), 0, st, w);
   switch (P.ty.kind) {
-    case 0: LAUNCH(PK_CLASSIFY, k_wide_count<0>, dim3(w.W), dim3(NT), 0, st, w); break;
-    case 1: LAUNCH(PK_CLASSIFY, k_wide_count<1>, dim3(w.W), dim3(NT), 0, st, w); break;
-    default: LAUNCH(PK_CLASSIFY, k_wide_count<2>, dim3(w.W), dim3(NT), 0, st, w); break;
+    case 0: LAUNCH(PK_CLASSIFY, k_wide_count<0>, dim3(w.W), dim3(CNT_NT), 0, st, w); break;
+    case 1: LAUNCH(PK_CLASSIFY, k_wide_count<1>, dim3(w.W), dim3(CNT_NT), 0, st, w); break;
+    default: LAUNCH(PK_CLASSIFY, k_wide_count<2>, dim3(w.W), dim3(CNT_NT), 0, st, w); break;
   }
   LAUNCH_CHECK();
   const uint32_t nbf = (uint32_t)cdiv(nf, SCAN_BLOCK), nba = (uint32_t)cdiv(na, SCAN_BLOCK);
@@ -800,7 +800,7 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   LAUNCH(PK_SCAN, k_scan_partials, dim3(2), dim3(NT), 0, st, pf, nf, (const uint64_t*)nullptr, q);
   LAUNCH(PK_SCAN, k_scan_down, dim3(nbf + nba), dim3(NT), 0, st, w.hf, pf, nf, (const uint64_t*)nullptr, q);
   LAUNCH_CHECK();
-  LAUNCH(PK_SPLIT_COARSE, k_wide_split_a, dim3(w.W), dim3(NT), 0, st, w);
+  LAUNCH(PK_SPLIT_COARSE, k_wide_split_a, dim3(w.W), dim3(SA_NT), 0, st, w);
   LAUNCH_CHECK();
   // pieces of the second pass: at most one per WIDE_TB keys of each region, plus one per region
   const uint32_t pieces = (uint32_t)(cdiv(P.n, WIDE_TB) + WIDE_P1);

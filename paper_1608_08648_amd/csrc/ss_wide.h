@@ -230,28 +230,28 @@ __device__ __forceinline__ uint32_t wide_tie_bucket(const uint32_t* sk, const ui
 }
 
 // keys of one chunk, issued ahead of their use (prefetch into registers)
-template <int U>
+template <int U, int NTH = NT>
 __device__ __forceinline__ void wide_load(uint32_t (&k)[U], const uint32_t* src, uint32_t i0, uint32_t end) {
   const int t = threadIdx.x;
-  if (i0 + U * NT <= end) {
+  if (i0 + U * NTH <= end) {
 #pragma unroll
-    for (int u = 0; u < U; u++) k[u] = src[i0 + u * NT + t];
+    for (int u = 0; u < U; u++) k[u] = src[i0 + u * NTH + t];
   } else {
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const uint32_t i = i0 + u * NT + t;
+      const uint32_t i = i0 + u * NTH + t;
       k[u] = i < end ? src[i] : 0u;
     }
   }
 }
 
 // coarse-region bytes of one chunk (0xFF past the end)
-template <int U>
+template <int U, int NTH = NT>
 __device__ __forceinline__ void wide_load_b(uint32_t (&b)[U], const uint8_t* cb, uint32_t i0, uint32_t end) {
   const int t = threadIdx.x;
 #pragma unroll
   for (int u = 0; u < U; u++) {
-    const uint32_t i = i0 + u * NT + t;
+    const uint32_t i = i0 + u * NTH + t;
     b[u] = i < end ? (uint32_t)cb[i] : 0xFFu;
   }
 }
@@ -277,8 +277,12 @@ struct WideCountLds {
 // (equal to a splitter's key, which need the position) take the slower
 // exact paths, entered once per row of a wave that holds any.  (Two
 // work-groups per CU: 74 KB of LDS each.)
+// (1024 threads, eight keys each per chunk, at most 64 VGPRs: eight waves
+// per SIMD with two work-groups per CU)
+constexpr int CNT_NT = 1024, CNT_U = 8, CNT_CH = CNT_NT * CNT_U;
+static_assert(CNT_CH * 7 == (int)WIDE_TILE, "a tile is seven chunks");
 template <int KIND>
-__global__ void __launch_bounds__(NT, 4) k_wide_count(WideArgs w) {
+__global__ void __launch_bounds__(CNT_NT, 8) k_wide_count(WideArgs w) {
   __shared__ WideCountLds sm;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= w.W) return;
@@ -286,28 +290,28 @@ __global__ void __launch_bounds__(NT, 4) k_wide_count(WideArgs w) {
   const uint32_t p = w.p, lg2 = w.lgp - WIDE_LG1;
   const uint32_t t0 = tile * w.tile, t1 = min(t0 + w.tile, w.n);
   const uint32_t* src = (const uint32_t*)w.src;
-  uint32_t nk[WIDE_U];
-  wide_load(nk, src, t0, t1);
+  uint32_t nk[CNT_U];
+  wide_load<CNT_U, CNT_NT>(nk, src, t0, t1);
   const uint32_t* stg = w.stags;   // tags: only tie keys read them (from L2)
   // the splitter keys and the cell table: every load issued before the
   // first LDS store (one round trip, not one per loop step)
   {
-    constexpr int RS = WIDE_PMAX / NT, RC = (WIDE_CELLS + 1 + NT - 1) / NT;
+    constexpr int RS = WIDE_PMAX / CNT_NT, RC = (WIDE_CELLS + 1 + CNT_NT - 1) / CNT_NT;
     const WideHdr h0 = *w.hdr;
     uint32_t vs[RS], vc[RC];
 #pragma unroll
     for (int r = 0; r < RS; r++) {
-      const uint32_t k = r * NT + t;
+      const uint32_t k = r * CNT_NT + t;
       vs[r] = k < p ? w.skeys[k] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < RC; r++) {
-      const uint32_t j = r * NT + t;
+      const uint32_t j = r * CNT_NT + t;
       vc[r] = j <= h0.ncell ? w.cells[j] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < RS; r++) {
-      const uint32_t k = r * NT + t;
+      const uint32_t k = r * CNT_NT + t;
       if (k < p) {
         sm.sk[k] = vs[r];
         sm.ties[k] = 0;
@@ -316,7 +320,7 @@ __global__ void __launch_bounds__(NT, 4) k_wide_count(WideArgs w) {
     }
 #pragma unroll
     for (int r = 0; r < RC; r++) {
-      const uint32_t j = r * NT + t;
+      const uint32_t j = r * CNT_NT + t;
       if (j <= h0.ncell) sm.cells[j] = vc[r];
     }
   }
@@ -326,27 +330,27 @@ __global__ void __launch_bounds__(NT, 4) k_wide_count(WideArgs w) {
   __syncthreads();
   uint32_t hint = ~0u;               // bucket of this thread's previous tie key
   const uint64_t all = __ballot(1);
-  for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_CH) {
-    uint32_t key[WIDE_U], cv[WIDE_U], c1[WIDE_U], c2[WIDE_U];
+  for (uint32_t i0 = t0; i0 < t1; i0 += CNT_CH) {
+    uint32_t key[CNT_U], cv[CNT_U], c1[CNT_U], c2[CNT_U];
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) key[u] = to_ord(nk[u], KIND);
-    if (i0 + WIDE_CH < t1) wide_load(nk, src, i0 + WIDE_CH, t1);
+    for (int u = 0; u < CNT_U; u++) key[u] = to_ord(nk[u], KIND);
+    if (i0 + CNT_CH < t1) wide_load<CNT_U, CNT_NT>(nk, src, i0 + CNT_CH, t1);
     // cell of every key (below the range: cell 0; above it: the sentinel
     // cell, whose first count is p - 1)
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) {
+    for (int u = 0; u < CNT_U; u++) {
       const uint32_t d = max(key[u], h.kmin) - h.kmin;
       cv[u] = sm.cells[min(d >> h.sh, h.ncell)];
     }
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) {
+    for (int u = 0; u < CNT_U; u++) {
       const uint32_t L = cv[u] & 0xFFFFu;
       c1[u] = sm.sk[L + 1];
       c2[u] = sm.sk[L + 2];
     }
 #pragma unroll
-    for (int u = 0; u < WIDE_U; u++) {
-      const uint32_t i = i0 + u * NT + t;
+    for (int u = 0; u < CNT_U; u++) {
+      const uint32_t i = i0 + u * CNT_NT + t;
       const bool valid = i < t1;
       const uint32_t k = key[u];
       const uint32_t L = cv[u] & 0xFFFFu, len = (cv[u] >> 16) - L;
@@ -397,16 +401,16 @@ __global__ void __launch_bounds__(NT, 4) k_wide_count(WideArgs w) {
   }
   __syncthreads();
   const uint32_t R = w.W + 2;
-  for (uint32_t b = t; b < p; b += NT) {
+  for (uint32_t b = t; b < p; b += CNT_NT) {
     w.hf[(uint64_t)b * R + 1 + tile] = (sm.cnt[b >> 1] >> (16 * (b & 1))) & 0xFFFFu;
     const uint32_t tl = sm.ties[b] & 0xFFFFu, th = sm.ties[b] >> 16;
     if (tl) atomicAdd(&w.hf[(uint64_t)b * R], tl);
     if (th) atomicAdd(&w.hf[(uint64_t)b * R + R - 1], th);
   }
-  // non-tie keys per coarse bucket: each thread sums p / NT consecutive fine
-  // counts (all inside one coarse bucket, as p / NT <= p / P1)
+  // non-tie keys per coarse bucket: each thread sums p / CNT_NT consecutive
+  // fine counts (all inside one coarse bucket, as p / CNT_NT <= p / P1)
   {
-    const uint32_t K = p / NT, P2 = p >> WIDE_LG1;
+    const uint32_t K = p / CNT_NT, P2 = p >> WIDE_LG1;
     uint32_t s = 0;
     for (uint32_t j = 0; j < K; j++) {
       const uint32_t b = t * K + j;
@@ -420,18 +424,18 @@ __global__ void __launch_bounds__(NT, 4) k_wide_count(WideArgs w) {
 
 // Grouping of one chunk by bucket in LDS, then contiguous run writes:
 // shared by both passes (NB buckets; bucket ~0u = key not moved).
-template <int NB, int U = WIDE_U>
+template <int NB, int U = WIDE_U, int NTH = NT>
 struct WideSplitLds {
   uint32_t gofs[NB];       // before the first chunk: output position of each bucket's run;
                            // then output position - chunk position of the current chunk's run
   uint32_t cur[2][NB];     // chunk counts, then cursors (alternating chunks)
   uint32_t ctot[2];        // keys of the chunk that move
-  uint32_t sk[U * NT];
-  uint8_t sb[U * NT];
+  uint32_t sk[U * NTH];
+  uint8_t sb[U * NTH];
 };
 
-template <int NB, int U>
-__device__ __forceinline__ void wide_group_write(WideSplitLds<NB, U>& sm, const uint32_t (&key)[U],
+template <int NB, int U, int NTH>
+__device__ __forceinline__ void wide_group_write(WideSplitLds<NB, U, NTH>& sm, const uint32_t (&key)[U],
                                                  const uint32_t (&bk)[U], uint32_t* dst, int x, bool first) {
   const int t = threadIdx.x;
   // sorted or constant input puts a wave's row of 64 keys into one bucket:
@@ -486,27 +490,30 @@ __device__ __forceinline__ void wide_group_write(WideSplitLds<NB, U>& sm, const 
   __syncthreads();
   const uint32_t tot = sm.ctot[x];
 #pragma unroll 4
-  for (uint32_t j = t; j < tot; j += NT) dst[sm.gofs[sm.sb[j]] + j] = sm.sk[j];
+  for (uint32_t j = t; j < tot; j += NTH) dst[sm.gofs[sm.sb[j]] + j] = sm.sk[j];
 }
 
+// (the first pass: 1024 threads, eight keys each per chunk, at most 64
+// VGPRs: eight waves per SIMD with two work-groups per CU)
+constexpr int SA_NT = 1024, SA_U = 8;
 struct WideALds {
-  WideSplitLds<WIDE_P1, WIDE_UA1> g;
+  WideSplitLds<WIDE_P1, SA_U, SA_NT> g;
 };
 
 // First pass, per input tile: non-tie keys to their coarse region, in runs.
 // The region comes from the classification's byte per key (the fine bucket's
 // top bits; 0xFF: a tie key, which stays where it is), so the keys are not
 // searched again.
-__global__ void __launch_bounds__(NT) k_wide_split_a(WideArgs w) {
+__global__ void __launch_bounds__(SA_NT, 8) k_wide_split_a(WideArgs w) {
   __shared__ WideALds sm;
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= w.W) return;
   const int t = threadIdx.x;
   const uint32_t t0 = tile * w.tile, t1 = min(t0 + w.tile, w.n);
   const uint32_t* src = (const uint32_t*)w.src;
-  uint32_t nk[WIDE_UA1], nb[WIDE_UA1];
-  wide_load(nk, src, t0, t1);
-  wide_load_b(nb, w.cb, t0, t1);
+  uint32_t nk[SA_U], nb[SA_U];
+  wide_load<SA_U, SA_NT>(nk, src, t0, t1);
+  wide_load_b<SA_U, SA_NT>(nb, w.cb, t0, t1);
   if (t < (int)WIDE_P1) {
     sm.g.gofs[t] = w.ha[(uint64_t)t * w.W + tile];
     sm.g.cur[0][t] = 0;
@@ -514,15 +521,15 @@ __global__ void __launch_bounds__(NT) k_wide_split_a(WideArgs w) {
   }
   __syncthreads();
   int x = 0;
-  for (uint32_t i0 = t0; i0 < t1; i0 += WIDE_UA1 * NT, x ^= 1) {
-    uint32_t key[WIDE_UA1], c[WIDE_UA1];
+  for (uint32_t i0 = t0; i0 < t1; i0 += SA_U * SA_NT, x ^= 1) {
+    uint32_t key[SA_U], c[SA_U];
 #pragma unroll
-    for (int u = 0; u < WIDE_UA1; u++) key[u] = to_ord(nk[u], w.kin);
+    for (int u = 0; u < SA_U; u++) key[u] = to_ord(nk[u], w.kin);
 #pragma unroll
-    for (int u = 0; u < WIDE_UA1; u++) c[u] = (i0 + u * NT + t < t1 && nb[u] != 0xFFu) ? nb[u] : ~0u;
-    if (i0 + WIDE_UA1 * NT < t1) {
-      wide_load(nk, src, i0 + WIDE_UA1 * NT, t1);
-      wide_load_b(nb, w.cb, i0 + WIDE_UA1 * NT, t1);
+    for (int u = 0; u < SA_U; u++) c[u] = (i0 + u * SA_NT + t < t1 && nb[u] != 0xFFu) ? nb[u] : ~0u;
+    if (i0 + SA_U * SA_NT < t1) {
+      wide_load<SA_U, SA_NT>(nk, src, i0 + SA_U * SA_NT, t1);
+      wide_load_b<SA_U, SA_NT>(nb, w.cb, i0 + SA_U * SA_NT, t1);
     }
     wide_group_write(sm.g, key, c, w.stage, x, i0 == t0);
   }
