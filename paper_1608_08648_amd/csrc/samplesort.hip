@@ -735,6 +735,9 @@ LevelArgs level_args(const Plan& P, char* ws, int l, const void* in, const void*
   return a;
 }
 
+// scans of up to this many blocks per array skip the partials launch
+constexpr uint32_t SCAN_SELF_MAX = 2048;
+
 uint32_t grid_of(uint64_t work, uint32_t per, uint32_t cap) {
   uint64_t g = cdiv(std::max<uint64_t>(work, 1), per);
   return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(g, 1), cap);
@@ -797,8 +800,10 @@ int run_wide(const Plan& P, char* ws, LevelArgs a, const void* in, void* out, in
   q.total2 = na;
   q.nb1 = nbf;
   LAUNCH(PK_SCAN, k_scan_reduce, dim3(nbf + nba), dim3(NT), 0, st, w.hf, pf, nf, (const uint64_t*)nullptr, q);
-  LAUNCH(PK_SCAN, k_scan_partials, dim3(2), dim3(NT), 0, st, pf, nf, (const uint64_t*)nullptr, q);
-  LAUNCH(PK_SCAN, k_scan_down, dim3(nbf + nba), dim3(NT), 0, st, w.hf, pf, nf, (const uint64_t*)nullptr, q);
+  // (arrays of few blocks: each block adds up the block sums before it, no partials launch)
+  const int self = (nbf <= SCAN_SELF_MAX && nba <= SCAN_SELF_MAX) ? 1 : 0;
+  if (!self) LAUNCH(PK_SCAN, k_scan_partials, dim3(2), dim3(NT), 0, st, pf, nf, (const uint64_t*)nullptr, q);
+  LAUNCH(PK_SCAN, k_scan_down, dim3(nbf + nba), dim3(NT), 0, st, w.hf, pf, nf, (const uint64_t*)nullptr, q, self);
   LAUNCH_CHECK();
   LAUNCH(PK_SPLIT_COARSE, k_wide_split_a, dim3(w.W), dim3(SA_NT), 0, st, w);
   LAUNCH_CHECK();
@@ -997,8 +1002,11 @@ int run_levels(const Plan& P, char* ws, const void* in, const void* vin, void* o
     const uint64_t* tot_dev = &a.ctl->total_hist;
     LAUNCH(PK_SCAN, k_scan_reduce, dim3(nb), dim3(NT), 0, st, a.hist, a.scan_part, (uint64_t)0, tot_dev,
            ScanPair{});
-    LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, a.scan_part, (uint64_t)0, tot_dev, ScanPair{});
-    LAUNCH(PK_SCAN, k_scan_down, dim3(nb), dim3(NT), 0, st, a.hist, a.scan_part, (uint64_t)0, tot_dev, ScanPair{});
+    const int self = nb <= SCAN_SELF_MAX ? 1 : 0;
+    if (!self)
+      LAUNCH(PK_SCAN, k_scan_partials, dim3(1), dim3(NT), 0, st, a.scan_part, (uint64_t)0, tot_dev, ScanPair{});
+    LAUNCH(PK_SCAN, k_scan_down, dim3(nb), dim3(NT), 0, st, a.hist, a.scan_part, (uint64_t)0, tot_dev, ScanPair{},
+           self);
     LAUNCH_CHECK();
     if constexpr (VW == 0) {
       // keys only: equal keys are bit-identical, so placement order inside a bucket is free
@@ -1294,8 +1302,9 @@ int sort_strings(const void* recs, void* recs_out, int64_t* perm_out, size_t n, 
     q.nb1 = nb;
     uint32_t* fp = (uint32_t*)(b + S.o_fp);
     LAUNCH(PK_SCAN, k_scan_reduce, dim3(2 * nb), dim3(NT), 0, st, f, fp, tot1, (const uint64_t*)nullptr, q);
-    LAUNCH(PK_SCAN, k_scan_partials, dim3(2), dim3(NT), 0, st, fp, tot1, (const uint64_t*)nullptr, q);
-    LAUNCH(PK_SCAN, k_scan_down, dim3(2 * nb), dim3(NT), 0, st, f, fp, tot1, (const uint64_t*)nullptr, q);
+    const int self = nb <= SCAN_SELF_MAX ? 1 : 0;
+    if (!self) LAUNCH(PK_SCAN, k_scan_partials, dim3(2), dim3(NT), 0, st, fp, tot1, (const uint64_t*)nullptr, q);
+    LAUNCH(PK_SCAN, k_scan_down, dim3(2 * nb), dim3(NT), 0, st, f, fp, tot1, (const uint64_t*)nullptr, q, self);
     LAUNCH_CHECK();
     // how many strings sit in runs of equal prefixes, in how many runs
     uint32_t tot = 0, nruns = 0;

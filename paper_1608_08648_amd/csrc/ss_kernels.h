@@ -1117,13 +1117,24 @@ __global__ void __launch_bounds__(NT) k_scan_partials(uint32_t* part, uint64_t t
   }
 }
 
+// self_prefix: part holds the blocks' plain sums (no k_scan_partials
+// launch) and each block adds up those before it itself -- for arrays of a
+// few thousand blocks at most, whose partials are a few KB read from L2.
 __global__ void __launch_bounds__(NT) k_scan_down(uint32_t* h, uint32_t* part, uint64_t total_h,
-                                                  const uint64_t* total_dev, ScanPair q) {
+                                                  const uint64_t* total_dev, ScanPair q, int self_prefix) {
   __shared__ uint32_t sh[NT / WAVE + 2];
   uint64_t total = scan_len(total_h, total_dev);
   const uint32_t bid = scan_pick(h, part, total, q, blockIdx.x);
   uint64_t b0 = (uint64_t)bid * SCAN_BLOCK;
   if (b0 >= total) return;
+  uint32_t before;
+  if (self_prefix) {
+    uint32_t v = 0;
+    for (uint32_t j = threadIdx.x; j < bid; j += NT) v += part[j];
+    block_excl_scan<NT>(v, sh, &before);
+  } else {
+    before = part[bid];
+  }
   // thread t owns the SCAN_ITEMS consecutive entries starting at b0 + t*SCAN_ITEMS
   static_assert(SCAN_ITEMS == 8, "two 16-byte vectors per thread");
   const bool whole = b0 + SCAN_BLOCK <= total;
@@ -1143,7 +1154,7 @@ __global__ void __launch_bounds__(NT) k_scan_down(uint32_t* h, uint32_t* part, u
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; k++) s += v[k];
   uint32_t tot;
-  uint32_t run = block_excl_scan<NT>(s, sh, &tot) + part[bid];
+  uint32_t run = block_excl_scan<NT>(s, sh, &tot) + before;
   if (whole) {
     uint32_t o[SCAN_ITEMS];
 #pragma unroll
