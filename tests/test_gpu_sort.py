@@ -120,12 +120,27 @@ def test_stages_regular_lemma1():
 
 
 def test_big_sample_uses_multi_workgroup_merge():
-    """p*s beyond one work-group: chunked sample sort plus merge passes."""
+    """p*s beyond one work-group: chunk sorts, then ranks across chunks (the
+    4-byte sample of 131,071 records by chunk pairs, the 8-byte one of 16,383
+    records by lane groups)."""
     keys = rand_keys(2**22, np.int32, 17)
     st, info = _stage_check(keys, 4096, 32, 0, seed=3)
     assert info.m == 4096 * 32 - 1
     keys = rand_keys(2**20, np.uint64, 18)
     _stage_check(keys, 2048, 8, 0, seed=4)
+
+
+def test_big_sample_lane_ranks_and_nested_sort():
+    """4-byte samples past the chunk-pair ranks: 262,143 records (128 chunks
+    of 2K, ranked by lane groups on the packed records) and 2^21 - 1 records
+    (sorted as 64-bit keys by a nested sort).  Sample, splitters and counts
+    equal the oracle's stages."""
+    keys = rand_keys(2**22, np.int32, 21)
+    st, info = _stage_check(keys, 1024, 256, 0, seed=5)
+    assert info.m == 1024 * 256 - 1
+    keys = rand_keys(2**23, np.uint32, 22)
+    st, info = _stage_check(keys, 2048, 1024, 0, seed=6)
+    assert info.m == 2048 * 1024 - 1
 
 
 @pytest.mark.parametrize("dist", workloads.DISTRIBUTIONS)
