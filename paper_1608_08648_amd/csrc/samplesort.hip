@@ -497,7 +497,7 @@ int plan_single_t(Plan* P, uint64_t n, const Types& ty, const ss_params& prm) {
     P->o_wtags = L.take(4 * (size_t)p);
     P->o_wcells = L.take(4 * ((size_t)WIDE_CELLS + 1));
     P->o_whdr = L.take(sizeof(WideHdr));
-    P->o_wcb = L.take(n);
+    P->o_wcb = L.take(W * WIDE_TILE);   // (whole chunks: one 8-byte word per thread per chunk)
   }
   // (the wide split's bucket sort takes any size in rounds; a level below
   // pays once buckets would need many rounds)

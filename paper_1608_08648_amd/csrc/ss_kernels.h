@@ -941,9 +941,9 @@ __global__ void __launch_bounds__(256) k_widen_index(const uint32_t* v32, int64_
     v64[i] = (int64_t)v32[i];
 }
 
-// A sample of 4-byte keys too large for the merge passes is sorted as
-// 64-bit keys (ord << 32) | tag, which order exactly as the records (key,
-// tag): pack before, unpack after.
+// A sample of 4-byte keys of 2^20 records or more (beyond what the chunk
+// ranks handle well) is sorted as 64-bit keys (ord << 32) | tag, which
+// order exactly as the records (key, tag): pack before, unpack after.
 constexpr uint64_t SAMPLE_NESTED_MIN = 1ull << 20;
 
 __global__ void __launch_bounds__(256) k_pack_sample(const uint32_t* so, const uint32_t* stag, uint64_t* pk,

@@ -47,7 +47,6 @@ constexpr int WIDE_PMAX = 4096;
 constexpr int WIDE_U = 16;                     // keys per thread per chunk
 constexpr int WIDE_CH = WIDE_U * NT;
 constexpr int WIDE_UA = 8;                      // keys per thread per chunk of the second pass (LDS)
-constexpr int WIDE_UA1 = 16;                    // keys per thread per chunk of the first pass (LDS)
 constexpr uint32_t WIDE_TILE = 7 * WIDE_U * 512; // keys per input tile (< 2^16: 16-bit tie counters)
 constexpr uint32_t WIDE_TB = 24576;            // nominal keys per piece of the second pass (small pieces: the
                                                // work-groups finish together)
@@ -245,15 +244,13 @@ __device__ __forceinline__ void wide_load(uint32_t (&k)[U], const uint32_t* src,
   }
 }
 
-// coarse-region bytes of one chunk (0xFF past the end)
-template <int U, int NTH = NT>
-__device__ __forceinline__ void wide_load_b(uint32_t (&b)[U], const uint8_t* cb, uint32_t i0, uint32_t end) {
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < U; u++) {
-    const uint32_t i = i0 + u * NTH + t;
-    b[u] = i < end ? (uint32_t)cb[i] : 0xFFu;
-  }
+// The coarse-region bytes of a chunk of 8 x 1024 keys: thread t's eight
+// keys (chunk positions u * 1024 + t) have theirs in one 8-byte word, the
+// chunk's word t, byte u (0xFF: a tie key, or past the end).  The
+// classification and the first split pass share that key-to-thread map.
+constexpr int CB_U = 8, CB_NT = 1024;
+__device__ __forceinline__ uint64_t wide_cb_word(const uint8_t* cb, uint32_t i0) {
+  return ((const uint64_t*)cb)[(i0 >> 3) + threadIdx.x];
 }
 
 struct WideCountLds {
@@ -330,8 +327,10 @@ __global__ void __launch_bounds__(CNT_NT, 8) k_wide_count(WideArgs w) {
   __syncthreads();
   uint32_t hint = ~0u;               // bucket of this thread's previous tie key
   const uint64_t all = __ballot(1);
+  static_assert(CNT_U == CB_U && CNT_NT == CB_NT, "the coarse-byte word layout");
   for (uint32_t i0 = t0; i0 < t1; i0 += CNT_CH) {
     uint32_t key[CNT_U], cv[CNT_U], c1[CNT_U], c2[CNT_U];
+    uint64_t cbw = 0;                // this thread's coarse-region bytes of the chunk
 #pragma unroll
     for (int u = 0; u < CNT_U; u++) key[u] = to_ord(nk[u], KIND);
     if (i0 + CNT_CH < t1) wide_load<CNT_U, CNT_NT>(nk, src, i0 + CNT_CH, t1);
@@ -382,7 +381,7 @@ __global__ void __launch_bounds__(CNT_NT, 8) k_wide_count(WideArgs w) {
           hint = b;
         }
       }
-      if (valid) w.cb[i] = tie ? (uint8_t)0xFFu : (uint8_t)(b >> lg2);
+      cbw |= (uint64_t)((valid && !tie) ? (b >> lg2) : 0xFFu) << (8 * u);
       // count: one atomic for a row of one (kind, bucket) (sorted or
       // constant input), else one per key
       const uint32_t idx = (kind << 16) | b;
@@ -398,6 +397,7 @@ __global__ void __launch_bounds__(CNT_NT, 8) k_wide_count(WideArgs w) {
         else atomicAdd(&sm.ties[b], kind == 1 ? 1u : 1u << 16);
       }
     }
+    ((uint64_t*)w.cb)[(i0 >> 3) + t] = cbw;
   }
   __syncthreads();
   const uint32_t R = w.W + 2;
@@ -511,9 +511,10 @@ __global__ void __launch_bounds__(SA_NT, 8) k_wide_split_a(WideArgs w) {
   const int t = threadIdx.x;
   const uint32_t t0 = tile * w.tile, t1 = min(t0 + w.tile, w.n);
   const uint32_t* src = (const uint32_t*)w.src;
-  uint32_t nk[SA_U], nb[SA_U];
+  static_assert(SA_U == CB_U && SA_NT == CB_NT, "the coarse-byte word layout");
+  uint32_t nk[SA_U];
   wide_load<SA_U, SA_NT>(nk, src, t0, t1);
-  wide_load_b<SA_U, SA_NT>(nb, w.cb, t0, t1);
+  uint64_t nbw = wide_cb_word(w.cb, t0);
   if (t < (int)WIDE_P1) {
     sm.g.gofs[t] = w.ha[(uint64_t)t * w.W + tile];
     sm.g.cur[0][t] = 0;
@@ -526,10 +527,13 @@ __global__ void __launch_bounds__(SA_NT, 8) k_wide_split_a(WideArgs w) {
 #pragma unroll
     for (int u = 0; u < SA_U; u++) key[u] = to_ord(nk[u], w.kin);
 #pragma unroll
-    for (int u = 0; u < SA_U; u++) c[u] = (i0 + u * SA_NT + t < t1 && nb[u] != 0xFFu) ? nb[u] : ~0u;
+    for (int u = 0; u < SA_U; u++) {
+      const uint32_t nb = (uint32_t)(nbw >> (8 * u)) & 0xFFu;
+      c[u] = (i0 + u * SA_NT + t < t1 && nb != 0xFFu) ? nb : ~0u;
+    }
     if (i0 + SA_U * SA_NT < t1) {
       wide_load<SA_U, SA_NT>(nk, src, i0 + SA_U * SA_NT, t1);
-      wide_load_b<SA_U, SA_NT>(nb, w.cb, i0 + SA_U * SA_NT, t1);
+      nbw = wide_cb_word(w.cb, i0 + SA_U * SA_NT);
     }
     wide_group_write(sm.g, key, c, w.stage, x, i0 == t0);
   }
