@@ -49,8 +49,8 @@ HBM_PEAK_GBS = 8000.0
 # on; "traffic" is null for anything else.
 MEASURED_TRAFFIC = {
     ("bucket_sort", 26, 4096, 16, "random", "uniform"): {
-        "src_sha256_16": "57e856fc7e45a759",
-        "bytes_per_launch": 830952205,   # k_wide_bucket<16000, 13>: FETCH 274,163 KiB x 2 + WRITE 263,152 KiB
+        "src_sha256_16": "4684226d8faef012",
+        "bytes_per_launch": 785994778,   # k_wide_bucket<16000, 13>: FETCH 221,407 KiB x 2 + WRITE 324,759 KiB
     },
 }
 

@@ -998,7 +998,7 @@ __device__ __forceinline__ void count_block(const LevelArgs& a, const TreeLds<KW
   for (int u = 0; u < U; u++) {
     uint32_t i = i0 + u * NT + threadIdx.x;
     tag[u] = i;
-    key[u] = (full || i < t1) ? to_ord(src[i], a.kin) : KT(0);
+    key[u] = (full || i < t1) ? to_ord(__builtin_nontemporal_load(&src[i]), a.kin) : KT(0);
   }
   tr.template classify_many<U>(key, tag, d.lgp, d.p, b);
 #pragma unroll
@@ -1351,7 +1351,7 @@ __device__ __forceinline__ void split_chunk(const LevelArgs& a, const SegDesc& d
   for (int u = 0; u < U; u++) {
     uint32_t i = u * NT + t;
     tag[u] = c0 + i;
-    key[u] = (FULL || i < cn) ? to_ord(src[c0 + i], a.kin) : KT(0);
+    key[u] = (FULL || i < cn) ? to_ord(__builtin_nontemporal_load(&src[c0 + i]), a.kin) : KT(0);
   }
   sm.tr.template classify_many<U>(key, tag, d.lgp, d.p, b);
   // sorted or constant input puts a wave's row of 64 keys into one bucket:
@@ -1492,7 +1492,9 @@ __device__ __forceinline__ void slot_rank_write(const typename KeyOf<KW>::T* pla
         rank += (o < k || (o == k && j < i)) ? 1u : 0u;
       }
     }
-    out[s0 + rank] = from_ord(k, kout);
+    // (streaming store: the output is not read again here, and the bucket's
+    // keys, which other rounds re-read, keep their place in L2)
+    __builtin_nontemporal_store(from_ord(k, kout), &out[s0 + rank]);
   }
 }
 

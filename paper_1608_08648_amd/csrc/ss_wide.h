@@ -228,18 +228,20 @@ __device__ __forceinline__ uint32_t wide_tie_bucket(const uint32_t* sk, const ui
   return a - 1;
 }
 
-// keys of one chunk, issued ahead of their use (prefetch into registers)
+// keys of one chunk, issued ahead of their use (prefetch into registers);
+// streaming loads: each key is read once per pass, so they need not stay in
+// L2, where the pass's tables and counts live
 template <int U, int NTH = NT>
 __device__ __forceinline__ void wide_load(uint32_t (&k)[U], const uint32_t* src, uint32_t i0, uint32_t end) {
   const int t = threadIdx.x;
   if (i0 + U * NTH <= end) {
 #pragma unroll
-    for (int u = 0; u < U; u++) k[u] = src[i0 + u * NTH + t];
+    for (int u = 0; u < U; u++) k[u] = __builtin_nontemporal_load(&src[i0 + u * NTH + t]);
   } else {
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const uint32_t i = i0 + u * NTH + t;
-      k[u] = i < end ? src[i] : 0u;
+      k[u] = i < end ? __builtin_nontemporal_load(&src[i]) : 0u;
     }
   }
 }
@@ -846,11 +848,11 @@ __global__ void __launch_bounds__(WIDE_BNT) k_wide_bucket(LevelArgs a, WideArgs 
   uint32_t* out = (uint32_t*)w.out;
   if (nt0 > beg) {
     const uint32_t v = from_ord(lo, w.kout);
-    for (uint32_t i = beg + t; i < nt0; i += WIDE_BNT) out[i] = v;
+    for (uint32_t i = beg + t; i < nt0; i += WIDE_BNT) __builtin_nontemporal_store(v, &out[i]);
   }
   if (end > nt1) {
     const uint32_t v = from_ord(hi, w.kout);
-    for (uint32_t i = nt1 + t; i < end; i += WIDE_BNT) out[i] = v;
+    for (uint32_t i = nt1 + t; i < end; i += WIDE_BNT) __builtin_nontemporal_store(v, &out[i]);
   }
   const uint32_t sz = nt1 - nt0;
   if (sz > WIDE_BMAX && a.next_segs) {

@@ -52,6 +52,9 @@ inline void __threadfence_block() { std::atomic_thread_fence(std::memory_order_s
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 inline void __builtin_amdgcn_wave_barrier() { g_emu_waves[threadIdx.x >> 6].bar.arrive_and_wait(); }
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
+// streaming (non-temporal) accesses are ordinary ones on the host
+#define __builtin_nontemporal_store(v, p) ((void)(*(p) = (v)))
+#define __builtin_nontemporal_load(p) (*(p))
 
 inline int emu_lane() { return threadIdx.x & 63; }
 
