@@ -49,8 +49,8 @@ HBM_PEAK_GBS = 8000.0
 # on; "traffic" is null for anything else.
 MEASURED_TRAFFIC = {
     ("bucket_sort", 26, 4096, 16, "random", "uniform"): {
-        "src_sha256_16": "4684226d8faef012",
-        "bytes_per_launch": 785994778,   # k_wide_bucket<16000, 13>: FETCH 221,407 KiB x 2 + WRITE 324,759 KiB
+        "src_sha256_16": "bd669cea9acc5a06",
+        "bytes_per_launch": 785098246,   # k_wide_bucket<16000, 13>: FETCH 220,955 KiB x 2 + WRITE 324,787 KiB
     },
 }
 

@@ -313,15 +313,16 @@ __device__ __forceinline__ void sort_small_k(const typename KeyOf<KW>::T* src, c
   const int t = threadIdx.x;
   VT* xv = (VT*)(void*)sm.xv;
   // striped (coalesced) load into LDS, then blocked registers; a bounded
-  // unroll keeps the number of in-flight load addresses in check
+  // unroll keeps the number of in-flight load addresses in check (each
+  // element is read and written once: streaming loads and stores)
 #pragma unroll 8
   for (int r = 0; r < K; r++) {
     int i = r * NT + t;
     int j = pad_idx<K>(i);
     if (i < (int)len) {
-      sm.xh[j] = to_ord(src[beg + i], kin);
+      sm.xh[j] = to_ord(__builtin_nontemporal_load(&src[beg + i]), kin);
       if constexpr (HASV) {
-        if (vsrc) xv[j] = ((const VT*)vsrc)[beg + i];
+        if (vsrc) xv[j] = __builtin_nontemporal_load(&((const VT*)vsrc)[beg + i]);
         else xv[j] = (VT)(iota_base + i);
       }
     } else {
@@ -345,8 +346,8 @@ __device__ __forceinline__ void sort_small_k(const typename KeyOf<KW>::T* src, c
     int i = r * NT + t;
     if (i < (int)len) {
       int j = pad_idx<K>(i);
-      out[beg + i] = from_ord(sm.xh[j], kout);
-      if constexpr (HASV) ((VT*)vout)[beg + i] = xv[j];
+      __builtin_nontemporal_store(from_ord(sm.xh[j], kout), &out[beg + i]);
+      if constexpr (HASV) __builtin_nontemporal_store(xv[j], &((VT*)vout)[beg + i]);
     }
   }
   __syncthreads();

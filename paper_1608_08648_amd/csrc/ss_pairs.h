@@ -123,6 +123,8 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
   __syncthreads();
   if (crowded) return false;
   // place (key, payload, position); afterwards each slot's counter holds its end
+  // (the last read of the bucket: streaming loads; the output, written once,
+  // leaves with streaming stores)
   for (uint32_t i0 = 0; i0 < len; i0 += 4 * NTH) {
     KT k[4];
     VT v[4];
@@ -132,8 +134,8 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
       v[u] = VT(0);
       if (i0 + u * NTH < len) {   // (rows wholly past the end load nothing)
         const uint32_t i = min(i0 + u * NTH + t, len - 1);
-        k[u] = in[i];
-        v[u] = vin[i];
+        k[u] = __builtin_nontemporal_load(&in[i]);
+        v[u] = __builtin_nontemporal_load(&vin[i]);
       }
     }
 #pragma unroll
@@ -169,8 +171,8 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
         rank += (ko < k || (ko == k && sm.pi[o] < ip)) ? 1u : 0u;
       }
     }
-    out[s0 + rank] = from_ord(k, kout);
-    vout[s0 + rank] = sm.pv[j];
+    __builtin_nontemporal_store(from_ord(k, kout), &out[s0 + rank]);
+    __builtin_nontemporal_store(sm.pv[j], &vout[s0 + rank]);
   }
   __syncthreads();
   return true;
