@@ -65,6 +65,34 @@ def test_level_counts_without_recursion_flag():
     assert len(levels) == 1
 
 
+@pytest.mark.parametrize("dtype", [np.int32, np.uint64])
+def test_pairs_without_recursion_merge_in_one_work_group(dtype):
+    """Stable pairs with SS_F_NO_RECURSION and p = 16 on 2^20 keys with many
+    duplicates: every bucket (~2^16 pairs) is past the stable slot sort, so
+    one work-group sorts it in LDS chunks and merges them through global
+    memory (reading back what it wrote); keys and an explicit payload must
+    equal the oracle's stable order."""
+    n = 1 << 20
+    g = np.random.default_rng(workloads.seed_for(7))
+    keys = g.integers(0, n // 8, size=n).astype(dtype)
+    vals = g.integers(0, 2**31 - 1, size=n).astype(np.int32)
+    perm = oracle.stable_perm(keys)
+    kd = torch.from_numpy(keys.view(np.int64) if dtype == np.uint64 else keys).cuda()
+    vd = torch.from_numpy(vals).cuda()
+    kt = N.SS_U64 if dtype == np.uint64 else N.SS_I32
+    prm = api.params(p=16, s=8, seed=5, flags=N.SS_F_NO_RECURSION)
+    ws = api._workspace(api.workspace_size(n, kt, N.SS_V_B32, prm), kd.device)
+    note(f"pairs no recursion 2^20 p=16 {np.dtype(dtype).name}")
+    ko, vo = api.sort_pairs(kd, vd, prm=prm, ws=ws, key_type="u64" if dtype == np.uint64 else None)
+    got = ko.cpu().numpy().view(dtype) if dtype == np.uint64 else ko.cpu().numpy()
+    np.testing.assert_array_equal(got, keys[perm])
+    np.testing.assert_array_equal(vo.cpu().numpy(), vals[perm])
+    levels = api.level_stats(ws)
+    assert len(levels) == 1
+    # the status notes the fallback (and nothing else): the path was taken
+    assert "0x2 " in api.status(ws), api.status(ws)
+
+
 def test_small_input_reports_no_level():
     """An input that one work-group sorts directly runs no split level."""
     keys = workloads.uniform_u32(1000, 5)
