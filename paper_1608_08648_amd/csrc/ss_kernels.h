@@ -1804,11 +1804,25 @@ __global__ void __launch_bounds__(NT) k_sort_small_list(Ctl* g, const SmallEnt* 
                                                         const void* vsrc, void* out, void* vout, int kind,
                                                         int iota) {
   using KT = typename KeyOf<KW>::T;
-  __shared__ SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> sm;
   if (blockIdx.x >= g->nsmall) return;
   SmallEnt e = list[blockIdx.x];
-  // an iota payload is the index inside the segment (0-based from e.beg)
-  sort_small<KW, VW>((const KT*)src, iota ? nullptr : vsrc, (KT*)out, vout, e.beg, e.len, 0, kind, kind, sm);
+  if constexpr (VW == 0) {
+    // keys only: the slot sort first (its LDS shares the radix sort's); a
+    // crowded segment, or one past its capacity, takes the radix sort
+    __shared__ union {
+      SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> r;
+      SlotLds<KW> q;
+    } u;
+    if (e.len <= (uint32_t)SlotLds<KW>::C &&
+        slot_sort<KW, NT, SlotCap<KW>::C>((const KT*)src, (KT*)out, e.beg, e.len, kind, kind, u.q))
+      return;
+    __syncthreads();
+    sort_small<KW, VW>((const KT*)src, nullptr, (KT*)out, vout, e.beg, e.len, 0, kind, kind, u.r);
+  } else {
+    __shared__ SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> sm;
+    // an iota payload is the index inside the segment (0-based from e.beg)
+    sort_small<KW, VW>((const KT*)src, iota ? nullptr : vsrc, (KT*)out, vout, e.beg, e.len, 0, kind, kind, sm);
+  }
 }
 
 // Segments of WAVE < len <= MID_CAP keys: the same LDS radix sort with
