@@ -1074,8 +1074,17 @@ int run_segmented(const Plan& P, char* ws, const void* in, const void* vin, void
     LAUNCH_CHECK();
   }
   if (P.maxlen > MID_CAP) {
-    LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)), dim3(NT), 0,
-           st, g, (const SmallEnt*)(ws + P.o_small), in, vin, out, vout, P.ty.kind, iota);
+    if constexpr (KW == 4 && VW == 4) {
+      if (iota)
+        LAUNCH(PK_SMALL_SORT, (k_sort_small_list_iota<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)),
+               dim3(NT), 0, st, g, (const SmallEnt*)(ws + P.o_small), in, out, vout, P.ty.kind);
+      else
+        LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)), dim3(NT),
+               0, st, g, (const SmallEnt*)(ws + P.o_small), in, vin, out, vout, P.ty.kind, iota);
+    } else {
+      LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)), dim3(NT), 0,
+             st, g, (const SmallEnt*)(ws + P.o_small), in, vin, out, vout, P.ty.kind, iota);
+    }
     LAUNCH_CHECK();
   }
   return run_levels<KW, VW>(P, ws, in, vin, out, vout, st);

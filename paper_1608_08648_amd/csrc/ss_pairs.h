@@ -19,34 +19,39 @@ template <int KW, int VW> struct StableSlotCap {
 };
 constexpr uint32_t STABLE_MAX_FILL = 64;   // crowded-slot limit
 
-template <int KW, int VW>
+// IOTA: the payload is the position inside the bucket (an in-segment
+// index), which the placed 16-bit position already holds: no payload array,
+// so 16384 4-byte keys fit (112 KB).
+template <int KW, int VW, bool IOTA = false>
 struct SlotStableLds {
   using KT = typename KeyOf<KW>::T;
   using VT = typename ValOf<VW>::T;
-  static constexpr int C = StableSlotCap<KW, VW>::C;
+  static constexpr int C = IOTA ? (KW == 4 ? 16384 : 8192) : StableSlotCap<KW, VW>::C;
   KT pk[C];
-  VT pv[C];
+  VT pv[IOTA ? 1 : C];
   uint16_t pi[C];
   uint32_t scnt[(1 << SLOT_LOG2) / 2];   // two 16-bit slot counters per word
   alignas(8) uint64_t red[64];
   uint32_t flag;
 };
 
-// Sorts in[0, len) (ord images) with payloads vin[0, len) into out / vout
-// (caller's key type), stable.  Returns false (having written nothing) when
-// the bucket is larger than the LDS or a slot is crowded.
-template <int KW, int VW, int NTH>
+// Sorts in[0, len) (key map kin: ord images by default) with payloads
+// vin[0, len) into out / vout (caller's key type), stable; IOTA: the payload
+// is the index in [0, len) and vin is not read.  Returns false (having
+// written nothing) when the bucket is larger than the LDS or a slot is
+// crowded.
+template <int KW, int VW, int NTH, bool IOTA = false>
 __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in, const typename ValOf<VW>::T* vin,
                                                  typename KeyOf<KW>::T* out, typename ValOf<VW>::T* vout,
-                                                 uint32_t len, int kout, SlotStableLds<KW, VW>& sm, bool lo_known,
-                                                 typename KeyOf<KW>::T lo, bool hi_known,
-                                                 typename KeyOf<KW>::T hi) {
+                                                 uint32_t len, int kout, SlotStableLds<KW, VW, IOTA>& sm,
+                                                 bool lo_known, typename KeyOf<KW>::T lo, bool hi_known,
+                                                 typename KeyOf<KW>::T hi, int kin = 0) {
   using KT = typename KeyOf<KW>::T;
   using VT = typename ValOf<VW>::T;
   constexpr int S = 1 << SLOT_LOG2;
   constexpr int W = S / 2;
   const int t = threadIdx.x;
-  if (len > (uint32_t)SlotStableLds<KW, VW>::C) return false;
+  if (len > (uint32_t)SlotStableLds<KW, VW, IOTA>::C) return false;
   // every key of the bucket to fn, eight per thread per step: whole steps
   // load without bounds tests, the last one clamps its index into the bucket
   auto each_key = [&](auto&& fn) {
@@ -54,7 +59,7 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
     for (; i0 + 8 * NTH <= len; i0 += 8 * NTH) {
       KT k[8];
 #pragma unroll
-      for (int u = 0; u < 8; u++) k[u] = in[i0 + u * NTH + t];
+      for (int u = 0; u < 8; u++) k[u] = to_ord(in[i0 + u * NTH + t], kin);
 #pragma unroll
       for (int u = 0; u < 8; u++) fn(k[u]);
     }
@@ -62,7 +67,7 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
       KT k[8] = {};
 #pragma unroll
       for (int u = 0; u < 8; u++)   // (rows wholly past the end load nothing)
-        if (i0 + u * NTH < len) k[u] = in[min(i0 + u * NTH + t, len - 1)];
+        if (i0 + u * NTH < len) k[u] = to_ord(in[min(i0 + u * NTH + t, len - 1)], kin);
 #pragma unroll
       for (int u = 0; u < 8; u++)
         if (i0 + u * NTH + t < len) fn(k[u]);
@@ -82,7 +87,7 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
   if (mn == mx) {                          // one key value: the bucket is in input order already
     for (uint32_t i = t; i < len; i += NTH) {
       out[i] = from_ord(mn, kout);
-      vout[i] = vin[i];
+      vout[i] = IOTA ? (VT)i : vin[i];
     }
     return true;
   }
@@ -134,8 +139,8 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
       v[u] = VT(0);
       if (i0 + u * NTH < len) {   // (rows wholly past the end load nothing)
         const uint32_t i = min(i0 + u * NTH + t, len - 1);
-        k[u] = __builtin_nontemporal_load(&in[i]);
-        v[u] = __builtin_nontemporal_load(&vin[i]);
+        k[u] = to_ord(__builtin_nontemporal_load(&in[i]), kin);
+        if constexpr (!IOTA) v[u] = __builtin_nontemporal_load(&vin[i]);
       }
     }
 #pragma unroll
@@ -146,7 +151,7 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
         const uint32_t sft = 16 * (q & 1);
         const uint32_t pos = (atomicAdd(&sm.scnt[q >> 1], 1u << sft) >> sft) & 0xFFFFu;
         sm.pk[pos] = k[u];
-        sm.pv[pos] = v[u];
+        if constexpr (!IOTA) sm.pv[pos] = v[u];
         sm.pi[pos] = (uint16_t)i;
       }
     }
@@ -172,10 +177,34 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
       }
     }
     __builtin_nontemporal_store(from_ord(k, kout), &out[s0 + rank]);
-    __builtin_nontemporal_store(sm.pv[j], &vout[s0 + rank]);
+    __builtin_nontemporal_store(IOTA ? (VT)ip : sm.pv[j], &vout[s0 + rank]);
   }
   __syncthreads();
   return true;
+}
+
+// Segments of the small class whose payload is their in-segment index
+// (4-byte keys; the blocks of the sort-first organisation and of regular
+// sampling, the row sort's short rows): the stable slot sort first, whose
+// placed positions are that payload, the radix sort when a segment is past
+// its LDS or a slot is crowded (the two share the LDS).
+template <int KW, int VW>
+__global__ void __launch_bounds__(NT) k_sort_small_list_iota(Ctl* g, const SmallEnt* list, const void* src, void* out,
+                                                             void* vout, int kind) {
+  using KT = typename KeyOf<KW>::T;
+  using VT = typename ValOf<VW>::T;
+  static_assert(KW == 4 && VW == 4, "4-byte keys with a 32-bit index");
+  __shared__ union {
+    SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> r;
+    SlotStableLds<KW, VW, true> q;
+  } u;
+  if (blockIdx.x >= g->nsmall) return;
+  const SmallEnt e = list[blockIdx.x];
+  if (slot_sort_stable<KW, VW, NT, true>((const KT*)src + e.beg, nullptr, (KT*)out + e.beg, (VT*)vout + e.beg, e.len,
+                                         kind, u.q, false, KT(0), false, KT(0), kind))
+    return;
+  __syncthreads();
+  sort_small<KW, VW>((const KT*)src, nullptr, (KT*)out, vout, e.beg, e.len, 0, kind, kind, u.r);
 }
 
 // Buckets of a split level (pairs): stable slot sort in LDS; buckets too
