@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(SF_GNT) k_sf_gather_any(SfArgs f, void* kstage
   __shared__ uint32_t offs[SF_PMAX + 1];   // start of run k in the bucket
   __shared__ uint32_t src[SF_PMAX];        // start of run k in the sorted blocks
   __shared__ uint32_t red[2 * (SF_GNT / WAVE)];
-  const uint32_t j = blockIdx.x, p = f.p;
+  const uint32_t j = xcd_tile(blockIdx.x, gridDim.x), p = f.p;   // (consecutive buckets on one XCD)
   if (j >= p) return;
   const int t = threadIdx.x;
   const uint32_t per = (p + SF_GNT - 1) / SF_GNT;
@@ -170,45 +170,93 @@ __global__ void __launch_bounds__(SF_GNT) k_sf_gather_any(SfArgs f, void* kstage
 // Step 5, first half: one work-group per bucket j finds its runs X_{k,j},
 // their places in the bucket (a scan over k) and the bucket's output start
 // (the keys of all blocks up to splitter j), and copies the runs, in block
-// order, to stage[start ..] as ord keys.
+// order, to stage[start ..] as ord keys.  Each wave copies a contiguous
+// range, one key per lane and step; a bitmap of the positions where a
+// non-empty run starts gives each lane its run: the wave's count of run
+// starts so far plus those among the lanes up to it (a bucket past the
+// bitmap finds each key's run by binary search instead).
+constexpr uint32_t SF_GMAP = 65536;        // bucket positions the run-start bitmap covers (8 KB)
+
 __global__ void __launch_bounds__(SF_GNT) k_sf_gather(SfArgs f, uint64_t* exp_counts) {
   __shared__ uint32_t off[SF_PMAX + 1];    // start of run k in the bucket
   __shared__ uint32_t src[SF_PMAX];        // start of run k in the sorted blocks
   __shared__ uint32_t red[2 * (SF_GNT / WAVE)];
-  const uint32_t j = blockIdx.x, p = f.p;
+  __shared__ uint16_t nz[SF_PMAX];         // k of the i-th non-empty run
+  __shared__ uint32_t bits[SF_GMAP / 32];  // bit e: a non-empty run starts at bucket position e
+  // consecutive buckets on one XCD: bucket j + 1's run of block k starts where
+  // bucket j's ends, so the cache lines of one bucket's runs serve the next
+  // from that XCD's L2
+  const uint32_t j = xcd_tile(blockIdx.x, gridDim.x), p = f.p;
   if (j >= p) return;
   const int t = threadIdx.x;
   const uint32_t per = (p + SF_GNT - 1) / SF_GNT;   // consecutive runs per thread
   const uint32_t k0 = min(p, (uint32_t)t * per), k1 = min(p, k0 + per);
-  uint32_t cnt = 0, below = 0;
+  uint32_t cnt = 0, below = 0, cnz = 0;
   for (uint32_t k = k0; k < k1; k++) {
     const uint32_t* row = f.pos + (uint64_t)k * (p + 1);
     const uint32_t a = row[j], b = row[j + 1];
     src[k] = (uint32_t)sf_block_start(f.n, p, k) + a;
     off[k] = b - a;            // (length until the scan)
     cnt += b - a;
+    cnz += b > a ? 1u : 0u;
     below += a;
   }
   uint32_t tot;
   uint32_t run = block_excl_scan<SF_GNT>(cnt, red, &tot);
   __syncthreads();
+  uint32_t nnz;
+  uint32_t zi = block_excl_scan<SF_GNT>(cnz, red, &nnz);
+  const bool mapped = tot <= SF_GMAP;
+  if (mapped)
+    for (uint32_t q = t; q < (tot + 31) / 32; q += SF_GNT) bits[q] = 0;
+  __syncthreads();
   for (uint32_t k = k0; k < k1; k++) {
     const uint32_t l = off[k];
     off[k] = run;
+    if (l) {
+      nz[zi++] = (uint16_t)k;
+      if (mapped) atomicOr(&bits[run >> 5], 1u << (run & 31));
+    }
     run += l;
   }
   if (t == 0) off[p] = tot;
   uint32_t start;
   block_excl_scan<SF_GNT>(below, red, &start);   // (total of the keys up to splitter j)
   __syncthreads();
-  for (uint32_t e = t; e < tot; e += SF_GNT) {
-    uint32_t a = 0, z = p;   // last run whose start is <= e
-    while (z - a > 1) {
-      const uint32_t m = (a + z) >> 1;
-      if (off[m] <= e) a = m;
-      else z = m;
+  if (mapped) {
+    constexpr uint32_t NW = SF_GNT / WAVE;
+    const uint32_t w = (uint32_t)t / WAVE, lane = (uint32_t)t % WAVE;
+    const uint64_t upto = lane == WAVE - 1 ? ~0ull : ((1ull << (lane + 1)) - 1);   // lanes <= this one
+    const uint32_t chunk = ((tot + NW - 1) / NW + WAVE - 1) / WAVE * WAVE;
+    const uint32_t e0 = min(tot, w * chunk), e1 = min(tot, e0 + chunk);
+    // runs that start before e0: the first i with off[nz[i]] >= e0
+    uint32_t lo = 0, hi = nnz;
+    while (lo < hi) {
+      const uint32_t m = (lo + hi) >> 1;
+      if (off[nz[m]] < e0) lo = m + 1;
+      else hi = m;
     }
-    f.stage[start + e] = to_ord(f.bkeys[src[a] + (e - off[a])], f.kind);
+    int base = (int)lo - 1;    // nz index of the run holding position e0 - 1
+    for (uint32_t e = e0 + lane; e - lane < e1; e += WAVE) {
+      const bool in = e < e1;
+      const bool st = in && ((bits[e >> 5] >> (e & 31)) & 1u);
+      const uint64_t m = __ballot(st);
+      if (in) {
+        const uint32_t a = nz[base + __popcll(m & upto)];   // the run holding position e
+        f.stage[start + e] = to_ord(f.bkeys[src[a] + (e - off[a])], f.kind);
+      }
+      base += __popcll(m);
+    }
+  } else {
+    for (uint32_t e = t; e < tot; e += SF_GNT) {
+      uint32_t a = 0, z = p;   // last run whose start is <= e
+      while (z - a > 1) {
+        const uint32_t m = (a + z) >> 1;
+        if (off[m] <= e) a = m;
+        else z = m;
+      }
+      f.stage[start + e] = to_ord(f.bkeys[src[a] + (e - off[a])], f.kind);
+    }
   }
   if (t == 0) {
     f.bkt[j] = make_uint2(start, tot);
@@ -304,7 +352,7 @@ __device__ __forceinline__ void sf_merge_round(const uint32_t* in, uint32_t* out
 
 __global__ void __launch_bounds__(SFM_NT) k_sf_merge(LevelArgs a, SfArgs f, uint64_t* exp_counts) {
   __shared__ SfMergeLds sm;
-  const uint32_t j = blockIdx.x, p = f.p;
+  const uint32_t j = xcd_tile(blockIdx.x, gridDim.x), p = f.p;   // (consecutive buckets on one XCD)
   if (j >= p) return;
   const int t = threadIdx.x;
   uint32_t* src = sm.buf[1];     // start of run k in the sorted blocks
