@@ -49,8 +49,8 @@ HBM_PEAK_GBS = 8000.0
 # on; "traffic" is null for anything else.
 MEASURED_TRAFFIC = {
     ("bucket_sort", 26, 4096, 16, "random", "uniform"): {
-        "src_sha256_16": "460e8ad3259ad8df",
-        "bytes_per_launch": 785253517,   # k_wide_bucket<16000, 13>: FETCH 220,993 KiB x 2 + WRITE 324,862 KiB
+        "src_sha256_16": "6c110c871a8fa614",
+        "bytes_per_launch": 786537094,   # k_wide_bucket<16000, 13>: FETCH 221,668 KiB x 2 + WRITE 324,766 KiB
     },
 }
 
