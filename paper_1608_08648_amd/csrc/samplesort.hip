@@ -372,6 +372,7 @@ struct Plan {
   size_t o_exp_so = 0, o_exp_st = 0, o_exp_po = 0, o_exp_pt = 0, o_exp_cnt = 0;
   bool exp = false;
   size_t o_small = 0, o_tiny = 0, o_mid = 0;   // segmented: lists of segments below one level
+  size_t o_small_fb = 0;                       // small segments handed from the stable slot sort to the radix sort
   // regular sampling: sorted blocks and the nested segmented plan
   size_t o_regk = 0, o_regi = 0, o_regoff = 0, o_nested = 0;
   Plan* nested = nullptr;
@@ -587,6 +588,7 @@ int plan_segmented_t(Plan* P, uint64_t total, uint64_t nseg, uint64_t maxlen, co
   Layout L;
   P->o_ctl = L.take(sizeof(Ctl));
   P->o_small = L.take(sizeof(SmallEnt) * std::max<uint64_t>(nseg, 1));
+  P->o_small_fb = L.take(sizeof(SmallEnt) * std::max<uint64_t>(nseg, 1));
   P->o_tiny = L.take(sizeof(SmallEnt) * std::max<uint64_t>(nseg, 1));
   P->o_mid = L.take(sizeof(SmallEnt) * std::max<uint64_t>(nseg, 1));
   P->s = prm.s;
@@ -1074,16 +1076,21 @@ int run_segmented(const Plan& P, char* ws, const void* in, const void* vin, void
     LAUNCH_CHECK();
   }
   if (P.maxlen > MID_CAP) {
+    const dim3 gs((uint32_t)std::max<uint64_t>(P.nseg, 1));
     if constexpr (KW == 4 && VW == 4) {
-      if (iota)
-        LAUNCH(PK_SMALL_SORT, (k_sort_small_list_iota<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)),
-               dim3(NT), 0, st, g, (const SmallEnt*)(ws + P.o_small), in, out, vout, P.ty.kind);
-      else
-        LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)), dim3(NT),
-               0, st, g, (const SmallEnt*)(ws + P.o_small), in, vin, out, vout, P.ty.kind, iota);
+      if (iota) {
+        LAUNCH(PK_SMALL_SORT, (k_sort_small_list_iota<KW, VW>), gs, dim3(WIDE_BNT), 0, st, g,
+               (const SmallEnt*)(ws + P.o_small), (SmallEnt*)(ws + P.o_small_fb), in, out, vout, P.ty.kind);
+        LAUNCH_CHECK();
+        LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), gs, dim3(NT), 0, st, g,
+               (const SmallEnt*)(ws + P.o_small_fb), in, vin, out, vout, P.ty.kind, iota, 1);
+      } else {
+        LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), gs, dim3(NT), 0, st, g, (const SmallEnt*)(ws + P.o_small),
+               in, vin, out, vout, P.ty.kind, iota, 0);
+      }
     } else {
-      LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), dim3((uint32_t)std::max<uint64_t>(P.nseg, 1)), dim3(NT), 0,
-             st, g, (const SmallEnt*)(ws + P.o_small), in, vin, out, vout, P.ty.kind, iota);
+      LAUNCH(PK_SMALL_SORT, (k_sort_small_list<KW, VW>), gs, dim3(NT), 0, st, g, (const SmallEnt*)(ws + P.o_small),
+             in, vin, out, vout, P.ty.kind, iota, 0);
     }
     LAUNCH_CHECK();
   }

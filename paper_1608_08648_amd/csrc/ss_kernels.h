@@ -101,6 +101,7 @@ struct Ctl {              // device control block at the start of the workspace
   uint32_t nsmall;        // entries in the small-segment list (up to one work-group's capacity)
   uint32_t ntiny;         // entries in the tiny-segment list (up to 64 keys: one wave each)
   uint32_t nmid;          // entries in the mid-segment list (up to MID_CAP keys: a small work-group each)
+  uint32_t nsmall_fb;     // small segments with an index payload the stable slot sort handed to the radix sort
   LevelCtl lv[MAX_LEVELS];
   uint32_t nleft[MAX_LEVELS];   // buckets the slot sort handed on, per level
   uint32_t nleft2[MAX_LEVELS];  // of those, buckets the round-based slot sort handed on
@@ -1802,9 +1803,10 @@ __global__ void k_seg_init(Ctl* g, const int64_t* off, uint32_t nseg, uint32_t C
 template <int KW, int VW>
 __global__ void __launch_bounds__(NT) k_sort_small_list(Ctl* g, const SmallEnt* list, const void* src,
                                                         const void* vsrc, void* out, void* vout, int kind,
-                                                        int iota) {
+                                                        int iota, int fb) {
   using KT = typename KeyOf<KW>::T;
-  if (blockIdx.x >= g->nsmall) return;
+  // (fb: the list of segments the stable slot sort handed on)
+  if (blockIdx.x >= (fb ? g->nsmall_fb : g->nsmall)) return;
   SmallEnt e = list[blockIdx.x];
   if constexpr (VW == 0) {
     // keys only: the slot sort first (its LDS shares the radix sort's); a

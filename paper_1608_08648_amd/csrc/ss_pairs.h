@@ -185,26 +185,23 @@ __device__ __forceinline__ bool slot_sort_stable(const typename KeyOf<KW>::T* in
 
 // Segments of the small class whose payload is their in-segment index
 // (4-byte keys; the blocks of the sort-first organisation and of regular
-// sampling, the row sort's short rows): the stable slot sort first, whose
-// placed positions are that payload, the radix sort when a segment is past
-// its LDS or a slot is crowded (the two share the LDS).
+// sampling, the row sort's short rows): the stable slot sort, whose placed
+// positions are that payload, with 1024 threads; a segment past its LDS or
+// with a crowded slot goes to the list `fb`, which the radix sort of the
+// small class takes next.
 template <int KW, int VW>
-__global__ void __launch_bounds__(NT) k_sort_small_list_iota(Ctl* g, const SmallEnt* list, const void* src, void* out,
-                                                             void* vout, int kind) {
+__global__ void __launch_bounds__(WIDE_BNT) k_sort_small_list_iota(Ctl* g, const SmallEnt* list, SmallEnt* fb,
+                                                                   const void* src, void* out, void* vout, int kind) {
   using KT = typename KeyOf<KW>::T;
   using VT = typename ValOf<VW>::T;
   static_assert(KW == 4 && VW == 4, "4-byte keys with a 32-bit index");
-  __shared__ union {
-    SmallLds<KW, VW, SmallCap<KW, VW>::KMAX> r;
-    SlotStableLds<KW, VW, true> q;
-  } u;
+  __shared__ SlotStableLds<KW, VW, true> sm;
   if (blockIdx.x >= g->nsmall) return;
   const SmallEnt e = list[blockIdx.x];
-  if (slot_sort_stable<KW, VW, NT, true>((const KT*)src + e.beg, nullptr, (KT*)out + e.beg, (VT*)vout + e.beg, e.len,
-                                         kind, u.q, false, KT(0), false, KT(0), kind))
-    return;
-  __syncthreads();
-  sort_small<KW, VW>((const KT*)src, nullptr, (KT*)out, vout, e.beg, e.len, 0, kind, kind, u.r);
+  if (!slot_sort_stable<KW, VW, WIDE_BNT, true>((const KT*)src + e.beg, nullptr, (KT*)out + e.beg,
+                                                (VT*)vout + e.beg, e.len, kind, sm, false, KT(0), false, KT(0), kind) &&
+      threadIdx.x == 0)
+    fb[atomicAdd(&g->nsmall_fb, 1u)] = e;
 }
 
 // Buckets of a split level (pairs): stable slot sort in LDS; buckets too
