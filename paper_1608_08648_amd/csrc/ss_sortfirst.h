@@ -73,7 +73,13 @@ __global__ void __launch_bounds__(SF_NT) k_sf_search(SfArgs f) {
     for (uint32_t i = threadIdx.x; i < len; i += SF_NT) sk[i] = to_ord(bkeys[bs + i], f.kind);
   __syncthreads();
   uint32_t* row = f.pos + (uint64_t)k * (f.p + 1);
-  for (uint32_t r = threadIdx.x; r <= f.p; r += SF_NT) {
+  // each thread takes consecutive splitters: the first by binary search, each
+  // later one by a galloping search from the previous one's place (the
+  // splitters are sorted, so their places are too)
+  const uint32_t per = (f.p + SF_NT) / SF_NT;   // (p + 1 entries)
+  const uint32_t r0 = threadIdx.x * per, r1 = min(f.p + 1, r0 + per);
+  uint32_t prev = 0;
+  for (uint32_t r = r0; r < r1; r++) {
     uint32_t res = len;
     if (r == 0) {
       res = 0;
@@ -90,16 +96,29 @@ __global__ void __launch_bounds__(SF_NT) k_sf_search(SfArgs f) {
         skey = f.tree[slot];
         stag = f.tree_tag[slot];
       }
-      uint32_t a = 0, z = len;   // first position whose key is above the splitter
+      // upto(m): the block's key m is not above the splitter; the answer is
+      // the first m in [prev, len) where it fails
+      auto upto = [&](uint32_t m) {
+        const KT km = lds ? sk[m] : to_ord(bkeys[bs + m], f.kind);
+        return km < skey || (km == skey && bs + f.bidx[bs + m] <= stag);
+      };
+      uint32_t a = prev, z = len;
+      if (r > r0) {   // gallop: widen [a, a + step) until it holds the answer
+        uint32_t step = 1;
+        while (a + step <= len && upto(a + step - 1)) {
+          a += step;
+          step *= 2;
+        }
+        z = min(len, a + step);
+      }
       while (a < z) {
         const uint32_t m = (a + z) >> 1;
-        const KT km = lds ? sk[m] : to_ord(bkeys[bs + m], f.kind);
-        const bool upto = km < skey || (km == skey && bs + f.bidx[bs + m] <= stag);
-        if (upto) a = m + 1;
+        if (upto(m)) a = m + 1;
         else z = m;
       }
       res = a;
     }
+    prev = res;
     row[r] = res;
   }
 }
