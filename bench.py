@@ -49,8 +49,8 @@ HBM_PEAK_GBS = 8000.0
 # on; "traffic" is null for anything else.
 MEASURED_TRAFFIC = {
     ("bucket_sort", 26, 4096, 16, "random", "uniform"): {
-        "src_sha256_16": "e03678c9b4e134b8",
-        "bytes_per_launch": 784751699,   # k_wide_bucket<16000, 13>: FETCH 220,624 KiB x 2 + WRITE 325,111 KiB
+        "src_sha256_16": "ecf97c174e6d229b",
+        "bytes_per_launch": 786305850,   # k_wide_bucket<16000, 13>: FETCH 221,542 KiB x 2 + WRITE 324,792 KiB
     },
 }
 
